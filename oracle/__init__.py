@@ -1,0 +1,341 @@
+"""FP64 CPU oracle for the cone-beam projector hot path -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and
+this package never imports the product: the two share nothing but the
+seeded input generators in ``synth``.
+
+The heavy ray operators are plain C (``ctoracle.c``, FP64, OpenMP); the
+iterative methods are written here in numpy, step by step, in the paper's
+order.  Every function names the passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+from synth import Ellipsoid, Geometry
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ctoracle.c")
+_LIB = os.path.join(_HERE, "libctoracle.so")
+
+SIDDON, INTERP = 0, 1
+_KINDS = {"siddon": SIDDON, "interp": INTERP}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Geo(ctypes.Structure):
+    _fields_ = [("DSD", ctypes.c_double), ("DSO", ctypes.c_double),
+                ("nz", ctypes.c_int64), ("ny", ctypes.c_int64), ("nx", ctypes.c_int64),
+                ("dz", ctypes.c_double), ("dy", ctypes.c_double), ("dx", ctypes.c_double),
+                ("oz", ctypes.c_double), ("oy", ctypes.c_double), ("ox", ctypes.c_double),
+                ("nv", ctypes.c_int64), ("nu", ctypes.c_int64),
+                ("dv", ctypes.c_double), ("du", ctypes.c_double),
+                ("ov", ctypes.c_double), ("ou", ctypes.c_double),
+                ("accuracy", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _lib.orc_wang_weight.restype = ctypes.c_double
+    return _lib
+
+
+def _geo(g: Geometry) -> _Geo:
+    return _Geo(g.DSD, g.DSO, *g.nVoxel, *g.dVoxel, *g.offOrigin, *g.nDetector, *g.dDetector,
+                *g.offDetector, g.accuracy)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def num_threads() -> int:
+    return int(_L().orc_num_threads())
+
+
+# ------------------------------------------------------------- operators
+def forward(geo: Geometry, angles, vol, kind: str = "siddon") -> np.ndarray:
+    """b = A x (the paper's linear model, section 2.1, Eq. 1)."""
+    angles = _f64(angles)
+    vol = _f64(vol).reshape(geo.nVoxel)
+    out = np.zeros((len(angles),) + tuple(geo.nDetector), dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_forward(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(vol), _p(out))
+    return out
+
+
+def backward(geo: Geometry, angles, proj, kind: str = "siddon") -> np.ndarray:
+    """x = A^T y, the exact transpose of `forward` (ray-driven scatter)."""
+    angles = _f64(angles)
+    proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
+    out = np.zeros(geo.nVoxel, dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_backward(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(proj), _p(out))
+    return out
+
+
+def forward_rays(geo: Geometry, angles, vol, views, ivs, ius, kind: str = "siddon") -> np.ndarray:
+    """(A x)_i for the listed rays only (sampled parity at full size)."""
+    angles = _f64(angles)
+    vol = _f64(vol).reshape(geo.nVoxel)
+    views, ivs, ius = _i64(views), _i64(ivs), _i64(ius)
+    out = np.zeros(len(views), dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_forward_rays(ctypes.byref(g), _KINDS[kind], _p(angles), _p(vol), ctypes.c_int64(len(views)),
+                          _p(views), _p(ivs), _p(ius), _p(out))
+    return out
+
+
+def adjoint_voxels(geo: Geometry, angles, proj, iz, iy, ix, kind: str = "siddon") -> np.ndarray:
+    """(A^T y)_j for the listed voxels, each matrix entry evaluated from its
+    definition (cell chord, or tent sum) by brute force over the voxel's
+    detector footprint."""
+    angles = _f64(angles)
+    proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
+    iz, iy, ix = _i64(iz), _i64(iy), _i64(ix)
+    out = np.zeros(len(iz), dtype=np.float64)
+    g = _geo(geo)
+    fn = _L().orc_siddon_adjoint_voxels if kind == "siddon" else _L().orc_interp_adjoint_voxels
+    fn(ctypes.byref(g), _p(angles), ctypes.c_int64(len(angles)), _p(proj), ctypes.c_int64(len(iz)),
+       _p(iz), _p(iy), _p(ix), _p(out))
+    return out
+
+
+def dense_matrix(geo: Geometry, angles, kind: str = "siddon") -> np.ndarray:
+    """Explicit system matrix, every entry from its definition (tiny sizes)."""
+    angles = _f64(angles)
+    nray = geo.n_proj(len(angles))
+    M = np.zeros((nray, geo.n_vox), dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_dense_matrix(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(M))
+    return M
+
+
+def ray_endpoints(geo: Geometry, theta: float, iv: float, iu: float):
+    """Source and pixel-centre positions (world mm) of ray (theta, iv, iu)."""
+    S = np.zeros(3)
+    P = np.zeros(3)
+    g = _geo(geo)
+    _L().orc_ray_endpoints(ctypes.byref(g), ctypes.c_double(theta), ctypes.c_double(iv), ctypes.c_double(iu),
+                           _p(S), _p(P))
+    return S, P
+
+
+# ------------------------------------------------------------------- FDK
+def bfdk(geo: Geometry, angles, proj) -> np.ndarray:
+    """FDK backprojector: sum over views of (DSO/U)^2 times the bilinear
+    detector sample where the source-voxel ray meets the detector (FDK, the
+    paper's list of direct methods in section 2.1)."""
+    angles = _f64(angles)
+    proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
+    out = np.zeros(geo.nVoxel, dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_bfdk(ctypes.byref(g), _p(angles), ctypes.c_int64(len(angles)), _p(proj), _p(out))
+    return out
+
+
+def fdk_filter(geo: Geometry, proj, ntotal: Optional[int] = None, wang: bool = False) -> np.ndarray:
+    """Cosine weight, optional Wang weight, Ram-Lak ramp (direct linear
+    convolution), angular scale."""
+    proj = _f64(proj)
+    nviews = proj.shape[0]
+    out = np.zeros_like(proj)
+    g = _geo(geo)
+    _L().orc_fdk_filter(ctypes.byref(g), ctypes.c_int64(nviews), ctypes.c_int64(ntotal or nviews),
+                        ctypes.c_int(1 if wang else 0), _p(proj), _p(out))
+    return out
+
+
+def wang_weight(geo: Geometry, u: float) -> float:
+    g = _geo(geo)
+    return float(_L().orc_wang_weight(ctypes.byref(g), ctypes.c_double(u)))
+
+
+def fdk(geo: Geometry, angles, proj, wang: bool = False) -> np.ndarray:
+    """FDK reconstruction = B_FDK(filter(proj))."""
+    q = fdk_filter(geo, proj, len(angles), wang)
+    return bfdk(geo, angles, q)
+
+
+# ----------------------------------------------------- iterative methods
+def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, mask=None):
+    """CGLS (Hestenes & Stiefel; the paper's Krylov methods, section 2.2.1).
+
+    x0 = 0; r = b - A x0; s = A^T r; p = s; gamma = |s|^2.  Each iteration:
+    q = A p; delta = |q|^2 (stop if 0); alpha = gamma / delta; x += alpha p;
+    r -= alpha q; s = A^T r; gamma' = |s|^2; beta = gamma'/gamma;
+    p = s + beta p.  Records |r_k| (the residual-norm history) and, given a
+    ground truth, |x_gt - x_k| and the PSNR (the error-norm history).
+    """
+    b = _f64(b)
+    x = np.zeros(geo.nVoxel)
+    r = b.copy()
+    s = backward(geo, angles, r, kind)
+    p = s.copy()
+    gamma = float(np.dot(s.ravel(), s.ravel()))
+    hist = {"resid": [], "err": [], "psnr": [], "alpha": [], "beta": [], "stopped": None}
+    for k in range(niter):
+        q = forward(geo, angles, p, kind)
+        delta = float(np.dot(q.ravel(), q.ravel()))
+        if delta == 0.0 or gamma == 0.0:
+            hist["stopped"] = k
+            break
+        alpha = gamma / delta
+        x = x + alpha * p
+        r = r - alpha * q
+        s = backward(geo, angles, r, kind)
+        gamma_new = float(np.dot(s.ravel(), s.ravel()))
+        beta = gamma_new / gamma
+        p = s + beta * p
+        gamma = gamma_new
+        hist["alpha"].append(alpha)
+        hist["beta"].append(beta)
+        hist["resid"].append(float(np.linalg.norm(r.ravel())))
+        if x_gt is not None:
+            hist["err"].append(float(np.linalg.norm((x - x_gt).ravel())))
+            hist["psnr"].append(psnr(x, x_gt, mask))
+    return x, hist
+
+
+def subsets(nviews: int, blocksize: int):
+    """Consecutive view blocks visited in order (the paper's ordered
+    subsets, section 2.2.2, sequential ordering)."""
+    return [np.arange(s, min(s + blocksize, nviews)) for s in range(0, nviews, blocksize)]
+
+
+def _recip0(a):
+    out = np.zeros_like(a)
+    nz = a != 0
+    out[nz] = 1.0 / a[nz]
+    return out
+
+
+def os_sart(geo: Geometry, angles, b, niter: int, blocksize: int, lam: float = 1.0, nonneg: bool = True,
+            kind: str = "interp", x0=None):
+    """OS-SART (ordered-subset step of section 2.2.2 with the row/column
+    length normalisation of SART).  The OS step is printed with the residual
+    as (A_s x - b_s); read as (b_s - A_s x), the descent direction.
+
+    Per block s: W = 1 / (A_s 1), V = 1 / (A_s^T 1) (0 where the sum is 0);
+    x <- x + lam * V (A_s^T (W (b_s - A_s x))); then x <- max(x, 0) if nonneg.
+    One iteration is one pass over all blocks.  SART is blocksize 1, SIRT
+    one block.
+    """
+    angles = _f64(angles)
+    b = _f64(b)
+    x = np.zeros(geo.nVoxel) if x0 is None else _f64(x0).copy()
+    blocks = subsets(len(angles), blocksize)
+    W, V = [], []
+    for idx in blocks:
+        a = angles[idx]
+        W.append(_recip0(forward(geo, a, np.ones(geo.nVoxel), kind)))
+        V.append(_recip0(backward(geo, a, np.ones((len(idx),) + tuple(geo.nDetector)), kind)))
+    for _ in range(niter):
+        for s, idx in enumerate(blocks):
+            a = angles[idx]
+            e = b[idx] - forward(geo, a, x, kind)
+            x = x + lam * V[s] * backward(geo, a, W[s] * e, kind)
+            if nonneg:
+                x = np.maximum(x, 0.0)
+    return x
+
+
+# --------------------------------------------------------------- metrics
+def fov_mask(geo: Geometry) -> np.ndarray:
+    """Voxels whose centre lies inside the volume's inscribed cylinder."""
+    nz, ny, nx = geo.nVoxel
+    dz, dy, dx = geo.dVoxel
+    y = (np.arange(ny) + 0.5 - ny / 2) * dy
+    x = (np.arange(nx) + 0.5 - nx / 2) * dx
+    m2 = (y[:, None] ** 2 + x[None, :] ** 2) <= geo.iso_fov_radius() ** 2
+    return np.broadcast_to(m2, (nz, ny, nx))
+
+
+def psnr(x, x_gt, mask=None) -> float:
+    """10 log10(R^2 / MSE) over the mask, R = the range of x_gt on the mask
+    (FP64).  Judges the error-norm history of the paper's section 2.2.3."""
+    x = _f64(x)
+    x_gt = _f64(x_gt)
+    if mask is None:
+        mask = np.ones(x.shape, dtype=bool)
+    d = (x - x_gt)[mask]
+    mse = float(np.mean(d * d))
+    g = x_gt[mask]
+    R = float(g.max() - g.min())
+    if mse == 0.0:
+        return math.inf
+    return 10.0 * math.log10(R * R / mse)
+
+
+# ---------------------------------------------------- analytic phantoms
+def ellipsoid_line_integrals(ellipsoids: Sequence[Ellipsoid], S: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """Closed-form line integrals of additive ellipsoids along segments
+    S -> P (arrays (..., 3), world mm).  In the ellipsoid's normalised frame
+    u = R^T (S - c) / a, w = R^T dhat / a; with A = w.w, B = u.w,
+    C = u.u - 1 the chord is 2 sqrt(B^2 - AC) / A when positive."""
+    S = np.asarray(S, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    d = P - S
+    L = np.linalg.norm(d, axis=-1, keepdims=True)
+    dh = d / L
+    out = np.zeros(S.shape[:-1])
+    for e in ellipsoids:
+        c = np.asarray(e.c)
+        a = np.asarray(e.a)
+        R = np.asarray(e.R)
+        u = ((S - c) @ R) / a
+        w = (dh @ R) / a
+        A = np.sum(w * w, -1)
+        B = np.sum(u * w, -1)
+        C = np.sum(u * u, -1) - 1.0
+        disc = B * B - A * C
+        chord = np.where(disc > 0, 2.0 * np.sqrt(np.maximum(disc, 0.0)) / A, 0.0)
+        out += e.rho * chord
+    return out
+
+
+def analytic_projections(geo: Geometry, angles, ellipsoids: Sequence[Ellipsoid]) -> np.ndarray:
+    """Closed-form cone-beam projections of an ellipsoid phantom, all rays."""
+    angles = _f64(angles)
+    nv, nu = geo.nDetector
+    out = np.zeros((len(angles), nv, nu))
+    iv, iu = np.meshgrid(np.arange(nv), np.arange(nu), indexing="ij")
+    for k, th in enumerate(angles):
+        c, s = math.cos(th), math.sin(th)
+        u = (iu + 0.5 - nu / 2) * geo.dDetector[1] + geo.offDetector[1]
+        v = (iv + 0.5 - nv / 2) * geo.dDetector[0] + geo.offDetector[0]
+        S = np.array([geo.DSO * c, geo.DSO * s, 0.0])
+        P = np.stack([S[0] - geo.DSD * c - u * s, S[1] - geo.DSD * s + u * c, v], -1)
+        out[k] = ellipsoid_line_integrals(ellipsoids, np.broadcast_to(S, P.shape), P)
+    return out

@@ -1,0 +1,484 @@
+"""Pins of the FP64 oracle to facts fixed by the mathematics, not by itself.
+
+Each test checks the oracle against a closed form, an invariant, a brute
+force evaluation on a tiny problem or a textbook/library routine, so that a
+dropped term, a wrong sign or index or a transposed operand in the oracle
+fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from synth import Ellipsoid, Geometry
+
+TINY = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(10, 12),
+                dDetector=(1.7, 1.6), offOrigin=(0.3, -0.4, 0.2), offDetector=(0.5, -0.7))
+TINY_ANISO = Geometry(DSD=70.0, DSO=45.0, nVoxel=(6, 8, 7), dVoxel=(1.2, 0.9, 1.1), nDetector=(9, 13),
+                      dDetector=(1.5, 1.3), offOrigin=(-0.2, 0.5, 0.1), offDetector=(-0.4, 0.3))
+
+
+def _angles(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.uniform(0, 2 * np.pi, n))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+# ------------------------------------------------------- Siddon, brute force
+@pytest.mark.parametrize("geo", [TINY, TINY_ANISO])
+def test_siddon_equals_cellwise_chords(orc, geo):
+    """Siddon's merged-crossing sum equals sum_j chord(ray, cell j) x_j where
+    every chord is a separate slab clip of the segment with one cell."""
+    ang = _angles(5, 1)
+    M = orc.dense_matrix(geo, ang, "siddon")
+    x = np.random.Generator(np.random.PCG64(2)).random(geo.nVoxel)
+    assert _rel(orc.forward(geo, ang, x, "siddon").ravel(), M @ x.ravel()) < 1e-12
+    # every ray's lengths add up to its chord through the volume box
+    assert _rel(M.sum(1), orc.forward(geo, ang, np.ones(geo.nVoxel), "siddon").ravel()) < 1e-12
+
+
+def test_siddon_row_vs_fine_sampling(orc):
+    """A matrix row against pure-numpy point sampling of the segment: the
+    fraction of 2e5 equispaced points falling into each cell times |P - S|."""
+    geo = TINY
+    ang = _angles(2, 3)
+    M = orc.dense_matrix(geo, ang, "siddon")
+    nz, ny, nx = geo.nVoxel
+    lo = np.array([geo.offOrigin[2] - nx * geo.dVoxel[2] / 2, geo.offOrigin[1] - ny * geo.dVoxel[1] / 2,
+                   geo.offOrigin[0] - nz * geo.dVoxel[0] / 2])
+    h = np.array([geo.dVoxel[2], geo.dVoxel[1], geo.dVoxel[0]])
+    npts = 200000
+    for k, iv, iu in [(0, 4, 5), (1, 2, 8), (0, 7, 3)]:
+        S, P = orc.ray_endpoints(geo, ang[k], iv, iu)
+        t = (np.arange(npts) + 0.5) / npts
+        X = S[None, :] + t[:, None] * (P - S)[None, :]
+        idx = np.floor((X - lo) / h).astype(int)
+        ok = np.all((idx >= 0) & (idx < np.array([nx, ny, nz])), 1)
+        lin = (idx[ok, 2] * ny + idx[ok, 1]) * nx + idx[ok, 0]
+        row = np.bincount(lin, minlength=geo.n_vox) * np.linalg.norm(P - S) / npts
+        r = (k * geo.nDetector[0] + iv) * geo.nDetector[1] + iu
+        assert np.max(np.abs(row - M[r])) < 2e-3
+        assert row.sum() > 1.0
+
+
+def _box_chord_np(S, P, bl, bh):
+    d = P - S
+    L = np.linalg.norm(d, axis=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a_lo = (bl - S) / d
+        a_hi = (bh - S) / d
+    a0 = np.max(np.minimum(a_lo, a_hi), axis=-1)
+    a1 = np.min(np.maximum(a_lo, a_hi), axis=-1)
+    a0 = np.maximum(a0, 0.0)
+    a1 = np.minimum(a1, 1.0)
+    return np.where(a1 > a0, (a1 - a0) * L, 0.0)
+
+
+def test_siddon_cuboid_phantom_exact(orc):
+    """Unions of whole voxels with constant densities: the ray sum is exactly
+    sum_b rho_b * (chord through block b), at any grid size."""
+    geo = Geometry(DSD=150.0, DSO=100.0, nVoxel=(24, 20, 22), dVoxel=(1.1, 0.9, 1.0), nDetector=(30, 40),
+                   dDetector=(1.3, 1.2), offOrigin=(0.4, -0.7, 0.9), offDetector=(0.6, -1.1))
+    ang = _angles(6, 5)
+    rng = np.random.Generator(np.random.PCG64(6))
+    x = np.zeros(geo.nVoxel)
+    blocks = []
+    for _ in range(5):
+        i0 = [int(rng.integers(0, n - 3)) for n in geo.nVoxel]
+        i1 = [int(rng.integers(a + 1, n + 1)) for a, n in zip(i0, geo.nVoxel)]
+        rho = float(rng.uniform(0.2, 1.0))
+        x[i0[0]:i1[0], i0[1]:i1[1], i0[2]:i1[2]] += rho
+        blocks.append((i0, i1, rho))
+    blocks.append(([0, 0, 0], list(geo.nVoxel), 0.05))   # the whole volume (x == 1 case)
+    x += 0.05
+    p = orc.forward(geo, ang, x, "siddon")
+    nz, ny, nx = geo.nVoxel
+    dz, dy, dx = geo.dVoxel
+    oz, oy, ox = geo.offOrigin
+    lo = np.array([ox - nx * dx / 2, oy - ny * dy / 2, oz - nz * dz / 2])
+    h = np.array([dx, dy, dz])
+    nv, nu = geo.nDetector
+    ref = np.zeros_like(p)
+    for k in range(len(ang)):
+        SP = [orc.ray_endpoints(geo, ang[k], iv, iu) for iv in range(nv) for iu in range(nu)]
+        S = np.array([a for a, _ in SP])
+        P = np.array([b for _, b in SP])
+        acc = np.zeros(len(SP))
+        for i0, i1, rho in blocks:
+            bl = lo + np.array([i0[2], i0[1], i0[0]]) * h
+            bh = lo + np.array([i1[2], i1[1], i1[0]]) * h
+            acc += rho * _box_chord_np(S, P, bl, bh)
+        ref[k] = acc.reshape(nv, nu)
+    assert np.max(np.abs(p - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------- interpolated, brute force
+@pytest.mark.parametrize("geo", [TINY, TINY_ANISO])
+def test_interp_equals_explicit_tent_matrix(orc, geo):
+    """Trilinear ray marching equals the matrix whose entries evaluate the
+    tent phi(c - j) directly for every (sample, voxel) pair."""
+    ang = _angles(5, 7)
+    M = orc.dense_matrix(geo, ang, "interp")
+    x = np.random.Generator(np.random.PCG64(8)).random(geo.nVoxel)
+    assert _rel(orc.forward(geo, ang, x, "interp").ravel(), M @ x.ravel()) < 1e-12
+    y = np.random.Generator(np.random.PCG64(9)).random((len(ang),) + geo.nDetector)
+    assert _rel(orc.backward(geo, ang, y, "interp").ravel(), M.T @ y.ravel()) < 1e-12
+
+
+def test_interp_sample_phase_anchored_at_source(orc):
+    """Samples sit at t_k = k ds from the source: moving the volume along an
+    oblique ray by a whole number of steps leaves that ray's sum unchanged,
+    and by a fraction of a step changes it."""
+    geo = Geometry(DSD=150.0, DSO=100.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(1, 1),
+                   dDetector=(1.0, 1.0), offDetector=(2.3, 3.1))
+    x = np.random.Generator(np.random.PCG64(10)).random(geo.nVoxel)
+    ang = np.array([0.3])
+    S, P = orc.ray_endpoints(geo, ang[0], 0.0, 0.0)
+    dh = (P - S) / np.linalg.norm(P - S)
+    p0 = orc.forward(geo, ang, x, "interp")[0, 0, 0]
+    assert p0 > 1.0
+    ds = geo.accuracy * 1.0
+    for shift in (ds * 3, -ds * 5):
+        g2 = geo.replace(offOrigin=tuple(shift * dh[::-1]))
+        assert abs(orc.forward(g2, ang, x, "interp")[0, 0, 0] - p0) < 1e-11 * abs(p0)
+    g3 = geo.replace(offOrigin=tuple(0.3 * ds * dh[::-1]))
+    assert abs(orc.forward(g3, ang, x, "interp")[0, 0, 0] - p0) > 1e-5 * abs(p0)
+
+
+# ----------------------------------------------------- transposes / adjoints
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_dot_product_identity(orc, kind):
+    geo = Geometry(DSD=150.0, DSO=100.0, nVoxel=(20, 24, 22), dVoxel=(1.0, 1.1, 0.9), nDetector=(28, 36),
+                   dDetector=(1.4, 1.3), offOrigin=(0.5, 0.2, -0.3), offDetector=(0.7, -0.4))
+    ang = _angles(9, 11)
+    rng = np.random.Generator(np.random.PCG64(12))
+    x = rng.random(geo.nVoxel)
+    y = rng.random((len(ang),) + geo.nDetector)
+    lhs = np.vdot(orc.forward(geo, ang, x, kind), y)
+    rhs = np.vdot(x, orc.backward(geo, ang, y, kind))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_scatter_transpose_equals_per_voxel_bruteforce(orc, kind):
+    """The ray-driven scatter A^T y against per-voxel brute force over each
+    voxel's detector footprint (different loop order, independent code)."""
+    geo = Geometry(DSD=150.0, DSO=100.0, nVoxel=(18, 20, 16), dVoxel=(1.0, 1.0, 1.2), nDetector=(26, 30),
+                   dDetector=(1.4, 1.3), offOrigin=(0.3, -0.2, 0.4), offDetector=(-0.6, 0.8))
+    ang = _angles(7, 13)
+    rng = np.random.Generator(np.random.PCG64(14))
+    y = rng.random((len(ang),) + geo.nDetector)
+    bt = orc.backward(geo, ang, y, kind)
+    sel = rng.integers(0, geo.n_vox, 300)
+    iz, iy, ix = np.unravel_index(sel, geo.nVoxel)
+    bf = orc.adjoint_voxels(geo, ang, y, iz, iy, ix, kind)
+    assert _rel(bf, bt.ravel()[sel]) < 1e-12
+
+
+# -------------------------------------------------------------- equivariance
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_rotation_and_flip_equivariance(orc, kind):
+    """Rotating the object by +90 deg about z equals shifting the view index
+    by -N/4; flipping z equals flipping the detector's v axis."""
+    geo = Geometry(DSD=150.0, DSO=100.0, nVoxel=(14, 16, 16), dVoxel=(1.0, 1.0, 1.0), nDetector=(20, 26),
+                   dDetector=(1.2, 1.3), offDetector=(0.0, 0.45))
+    N = 8
+    ang = synth.circular_angles(N)
+    x = np.random.Generator(np.random.PCG64(15)).random(geo.nVoxel)
+    n = geo.nVoxel[2]
+    # new(X, Y) = old(Y, -X): new[:, iy, ix] = old[:, n - 1 - ix, iy]
+    iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    xr = x[:, n - 1 - ix, iy]
+    p = orc.forward(geo, ang, x, kind)
+    pr = orc.forward(geo, ang, xr, kind)
+    assert _rel(pr, np.roll(p, N // 4, axis=0)) < 1e-12
+    assert _rel(pr, p) > 1e-3
+    pz = orc.forward(geo, ang, x[::-1], kind)
+    assert _rel(pz, p[:, ::-1, :]) < 1e-12
+
+
+# ------------------------------------------------------ continuum convergence
+def _phantom_64mm():
+    g = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(64, 64, 64), dVoxel=(1.0, 1.0, 1.0), nDetector=(48, 48),
+                 dDetector=(2.0, 2.0))
+    return synth.random_ellipsoids(g, seed=21, count_range=(6, 8), axis_range=(6.0, 18.0))
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_ellipsoid_closed_form_convergence(orc, kind):
+    """Projections of the voxelised phantom converge to the closed-form line
+    integrals as the grid is refined (same physical object and detector)."""
+    ell = _phantom_64mm()
+    ang = _angles(6, 22)
+    errs = []
+    for n in (16, 32, 64):
+        d = 64.0 / n
+        geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(n, n, n), dVoxel=(d, d, d), nDetector=(48, 48),
+                       dDetector=(2.0, 2.0))
+        x = synth.voxelize(geo, ell, sub=4, dtype=np.float64)
+        p = orc.forward(geo, ang, x, kind)
+        pa = orc.analytic_projections(geo, ang, ell)
+        errs.append(_rel(p, pa))
+    order = math.log2(errs[0] / errs[2]) / 2
+    assert errs[0] > errs[1] > errs[2]
+    assert order >= 0.8, (errs, order)
+    assert errs[2] < 0.06
+
+
+def test_ellipsoid_chord_closed_form():
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(23))
+    e = Ellipsoid((1.0, -2.0, 0.5), (7.0, 4.0, 5.0), tuple(map(tuple, np.linalg.qr(rng.normal(size=(3, 3)))[0])), 1.0)
+    npts = 400000
+    for _ in range(4):
+        S = rng.normal(size=3) * 3 + np.array([40.0, 0, 0])
+        P = rng.normal(size=3) * 3 + np.array([-40.0, 0, 0])
+        t = (np.arange(npts) + 0.5) / npts
+        X = S + t[:, None] * (P - S)
+        q = ((X - np.array(e.c)) @ np.array(e.R)) / np.array(e.a)
+        quad = np.mean(np.sum(q * q, 1) <= 1.0) * np.linalg.norm(P - S)
+        cf = oracle.ellipsoid_line_integrals([e], S[None], P[None])[0]
+        assert abs(cf - quad) < 1e-3
+    # a sphere: chord 2 sqrt(r^2 - d^2) at distance d from the centre
+    sph = Ellipsoid((0.0, 0.0, 0.0), (5.0, 5.0, 5.0), ((1, 0, 0), (0, 1, 0), (0, 0, 1)), 2.0)
+    for dd in (0.0, 1.5, 4.9, 5.1):
+        S = np.array([[30.0, dd, 0.0]])
+        P = np.array([[-30.0, dd, 0.0]])
+        want = 2.0 * 2.0 * math.sqrt(max(25.0 - dd * dd, 0.0))
+        assert abs(oracle.ellipsoid_line_integrals([sph], S, P)[0] - want) < 1e-12
+
+
+# ------------------------------------------------------------------- FDK
+def _ball(r, c=(0.0, 0.0, 0.0), rho=1.0):
+    return Ellipsoid(c, (r, r, r), ((1, 0, 0), (0, 1, 0), (0, 0, 1)), rho)
+
+
+def test_fdk_uniform_ball(orc):
+    """A uniform unit-density ball reconstructs to 1 in its interior (FDK
+    scaling: cosine weight, Ram-Lak ramp, angular factor, (DSO/U)^2)."""
+    geo, _ = synth.workload("head64")
+    ang = synth.circular_angles(128)
+    R = 0.6 * geo.iso_fov_radius()
+    pa = orc.analytic_projections(geo, ang, [_ball(R)])
+    f = orc.fdk(geo, ang, pa)
+    nz, ny, nx = geo.nVoxel
+    yc = (np.arange(ny) + 0.5 - ny / 2)
+    xc = (np.arange(nx) + 0.5 - nx / 2)
+    r2 = yc[:, None] ** 2 + xc[None, :] ** 2
+    mid = f[nz // 2 - 1:nz // 2 + 1]
+    interior = mid[:, r2 < (0.8 * R) ** 2]
+    assert abs(interior.mean() - 1.0) < 0.01, interior.mean()
+    outside = mid[:, r2 > (1.2 * R) ** 2]
+    assert abs(outside.mean()) < 0.02
+
+
+def test_fdk_off_centre_ball_lands_in_place(orc):
+    """The reconstructed centroid of an off-centre ball is the ball centre:
+    the backprojector's detector mapping agrees with the ray geometry."""
+    geo, _ = synth.workload("head64")
+    geo = geo.replace(offOrigin=(1.5, -2.0, 3.0), offDetector=(0.8, -1.3))
+    ang = synth.circular_angles(96)
+    c = (9.0 + 3.0, -6.0 - 2.0, 4.0 + 1.5)
+    pa = orc.analytic_projections(geo, ang, [_ball(7.0, c)])
+    f = orc.fdk(geo, ang, pa)
+    f = np.where(f > 0.5, f, 0.0)
+    nz, ny, nx = geo.nVoxel
+    Z, Y, X = np.meshgrid((np.arange(nz) + 0.5 - nz / 2) + 1.5, (np.arange(ny) + 0.5 - ny / 2) - 2.0,
+                          (np.arange(nx) + 0.5 - nx / 2) + 3.0, indexing="ij")
+    m = f.sum()
+    cen = ((f * X).sum() / m, (f * Y).sum() / m, (f * Z).sum() / m)
+    assert np.allclose(cen, c, atol=0.15), cen
+
+
+def test_ramp_filter_frequency_response(orc):
+    """The Ram-Lak kernel is the band-limited ramp: a row cos(2 pi f u) is
+    returned scaled by |f| (away from the row ends), times the FDK angular
+    factor pi/N.  The geometry makes the cosine weight 1 to 1e-12."""
+    nu = 2048
+    geo = Geometry(DSD=2e7, DSO=1e7, nVoxel=(4, 4, 4), dVoxel=(1.0, 1.0, 1.0), nDetector=(1, nu),
+                   dDetector=(1.0, 1.0))
+    tau = geo.dDetector[1] * geo.DSO / geo.DSD
+    N = 7
+    u = (np.arange(nu) + 0.5 - nu / 2) * tau
+    for f in (0.02, 0.11, 0.37, 0.93):           # cycles per mm at iso (Nyquist = 1 / (2 tau) = 1)
+        row = np.cos(2 * np.pi * f * u)
+        out = orc.fdk_filter(geo, np.tile(row, (N, 1, 1)), ntotal=N)[0, 0]
+        centre = slice(nu // 2 - 64, nu // 2 + 64)
+        want = abs(f) * row * (np.pi / N)
+        assert np.max(np.abs(out[centre] - want[centre])) < 2e-3 * (np.pi / N), f
+    # DC: the ramp removes the mean of a long constant row (up to the 1/n tail)
+    out = orc.fdk_filter(geo, np.ones((N, 1, nu)), ntotal=N)[0, 0]
+    assert abs(out[nu // 2]) < 1e-3 * (np.pi / N)
+
+
+def test_bfdk_constant_closed_form(orc):
+    """q == 1 on the detector: (B q)(X) = sum_k (DSO / (DSO - r cos(theta_k - phi)))^2,
+    which for N uniform views is N DSO^3 / (DSO^2 - r^2)^(3/2)."""
+    geo = Geometry(DSD=300.0, DSO=200.0, nVoxel=(6, 20, 20), dVoxel=(2.0, 2.0, 2.0), nDetector=(80, 120),
+                   dDetector=(1.5, 1.5))
+    N = 48
+    ang = synth.circular_angles(N)
+    out = orc.bfdk(geo, ang, np.ones((N,) + geo.nDetector))
+    yc = (np.arange(20) + 0.5 - 10) * 2.0
+    xc = (np.arange(20) + 0.5 - 10) * 2.0
+    r2 = yc[:, None] ** 2 + xc[None, :] ** 2
+    want = N * geo.DSO ** 3 / (geo.DSO ** 2 - r2) ** 1.5
+    assert np.max(np.abs(out / want[None] - 1.0)) < 1e-12
+
+
+def test_bfdk_impulse_matches_ray_geometry(orc):
+    """A single-pixel impulse backprojects onto voxel X with weight
+    (DSO/U)^2 * bilinear hat, where the detector position of X is found by
+    intersecting the line S-X with the detector plane spanned by the ray
+    end points (no formula shared with the oracle's backprojector)."""
+    geo = Geometry(DSD=300.0, DSO=200.0, nVoxel=(6, 8, 10), dVoxel=(2.0, 2.0, 2.0), nDetector=(40, 50),
+                   dDetector=(1.5, 1.5), offOrigin=(1.0, -2.0, 3.0), offDetector=(0.7, -0.9))
+    th = 0.7
+    nz, ny, nx = geo.nVoxel
+    S, P00 = orc.ray_endpoints(geo, th, 0.0, 0.0)
+    _, P01 = orc.ray_endpoints(geo, th, 0.0, 1.0)
+    _, P10 = orc.ray_endpoints(geo, th, 1.0, 0.0)
+    eu, ev = P01 - P00, P10 - P00
+    rng = np.random.Generator(np.random.PCG64(31))
+    for _ in range(6):
+        iz, iy, ix = int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))
+        X = np.array([3.0 - nx + 2.0 * ix + 1.0, -2.0 - ny + 2.0 * iy + 1.0, 1.0 - nz + 2.0 * iz + 1.0])
+        # solve S + t (X - S) = P00 + a eu + b ev
+        A = np.stack([X - S, -eu, -ev], 1)
+        t, fu, fv = np.linalg.solve(A, P00 - S)
+        iu, ivv = int(np.floor(fu)), int(np.floor(fv))
+        q = np.zeros((1,) + geo.nDetector)
+        q[0, ivv, iu] = 1.0
+        out = orc.bfdk(geo, np.array([th]), q)[iz, iy, ix]
+        nrm = np.cross(eu, ev)
+        U = np.dot(X - S, nrm) / np.dot(P00 - S, nrm) * geo.DSD    # distance along the axis
+        want = (geo.DSO * geo.DSD / U / geo.DSD) ** 2 * (1 - (fu - iu)) * (1 - (fv - ivv))
+        assert abs(out - want) < 1e-12 * max(want, 1e-3), (out, want)
+
+
+def test_wang_weight_partition_of_unity(orc):
+    geo, _ = synth.workload("large1024")
+    D = geo.nDetector[1] * geo.dDetector[1] / 2 - abs(geo.offDetector[1])
+    for u in np.linspace(-D, D, 41):
+        assert abs(orc.wang_weight(geo, u) + orc.wang_weight(geo, -u) - 1.0) < 1e-14
+    assert orc.wang_weight(geo, D + 1.0) == 1.0
+    assert orc.wang_weight(geo, -D - 1.0) == 0.0
+    assert abs(orc.wang_weight(geo, 0.0) - 0.5) < 1e-15
+
+
+def test_fdk_wang_offset_detector_ball(orc):
+    """Offset detector that sees only part of a ball in each view (shadow
+    half-width 40 mm, detector u in [-32.8, 56.8] mm): FDK with Wang weights
+    still reconstructs the unit density; without them it does not."""
+    geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(8, 64, 64), dVoxel=(1.0, 1.0, 1.0), nDetector=(16, 56),
+                   dDetector=(1.6, 1.6), offDetector=(0.0, 12.0))
+    ang = synth.circular_angles(180)
+    R = 26.0
+    pa = orc.analytic_projections(geo, ang, [_ball(R)])
+    f = orc.fdk(geo, ang, pa, wang=True)
+    yc = (np.arange(64) + 0.5 - 32)
+    r2 = yc[:, None] ** 2 + yc[None, :] ** 2
+    interior = f[3:5][:, r2 < (0.8 * R) ** 2]
+    assert abs(interior.mean() - 1.0) < 0.015, interior.mean()
+    nowang = orc.fdk(geo, ang, pa, wang=False)[3:5][:, r2 < (0.8 * R) ** 2]
+    assert abs(nowang.mean() - 1.0) > 0.05
+
+
+# ------------------------------------------------------------------ CGLS
+def _krylov_solutions(M, b, kmax):
+    """x_k = argmin_{x in K_k(M^T M, M^T b)} |M x - b|, orthonormal basis by
+    modified Gram-Schmidt (twice), then a dense least-squares solve."""
+    n = M.shape[1]
+    V = np.zeros((n, 0))
+    v = M.T @ b
+    sols = []
+    for _ in range(kmax):
+        for _ in range(2):
+            v = v - V @ (V.T @ v)
+        v = v / np.linalg.norm(v)
+        V = np.concatenate([V, v[:, None]], 1)
+        c, *_ = np.linalg.lstsq(M @ V, b, rcond=None)
+        sols.append(V @ c)
+        v = M.T @ (M @ v)
+    return sols
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_cgls_iterates_are_krylov_minimisers(orc, kind):
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 8),
+                   dDetector=(1.6, 1.6))
+    ang = synth.circular_angles(8)
+    rng = np.random.Generator(np.random.PCG64(41))
+    xt = rng.random(geo.nVoxel)
+    M = orc.dense_matrix(geo, ang, kind)
+    b = M @ xt.ravel() + 0.01 * rng.standard_normal(M.shape[0])
+    ref = _krylov_solutions(M, b, 8)
+    for k in range(1, 9):
+        xk, hist = orc.cgls(geo, ang, b.reshape((8,) + geo.nDetector), k, kind)
+        assert _rel(xk.ravel(), ref[k - 1]) < 1e-8, k
+    _, hist = orc.cgls(geo, ang, b.reshape((8,) + geo.nDetector), 12, kind, x_gt=xt)
+    res = hist["resid"]
+    assert all(res[i + 1] <= res[i] * (1 + 1e-12) for i in range(len(res) - 1))
+
+
+def test_cgls_norm_of_iterate_grows(orc):
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 8),
+                   dDetector=(1.6, 1.6))
+    ang = synth.circular_angles(6)
+    b = np.random.Generator(np.random.PCG64(42)).random((6, 8, 8))
+    norms = [np.linalg.norm(orc.cgls(geo, ang, b, k, "siddon")[0]) for k in range(1, 8)]
+    assert all(norms[i + 1] >= norms[i] * (1 - 1e-12) for i in range(len(norms) - 1))
+
+
+# --------------------------------------------------------------- OS-SART
+@pytest.mark.parametrize("blocksize", [1, 4, 12])
+def test_os_sart_converges_on_consistent_data(orc, blocksize):
+    """On noise-free data of a non-negative image, SART (blocksize 1),
+    OS-SART and SIRT (one block) drive the residual down monotonically per
+    pass, and the true image is a fixed point."""
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(6, 6, 6), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 8),
+                   dDetector=(1.4, 1.4))
+    ang = synth.circular_angles(12)
+    xt = np.random.Generator(np.random.PCG64(43)).random(geo.nVoxel)
+    b = orc.forward(geo, ang, xt, "interp")
+    res = []
+    x = None
+    for it in range(6):
+        x = orc.os_sart(geo, ang, b, 1, blocksize, x0=x, kind="interp")
+        res.append(np.linalg.norm(orc.forward(geo, ang, x, "interp") - b))
+    assert all(res[i + 1] < res[i] for i in range(len(res) - 1)), res
+    assert res[-1] < 0.5 * res[0]
+    xf = orc.os_sart(geo, ang, b, 1, blocksize, x0=xt, kind="interp")
+    assert _rel(xf, xt) < 1e-12
+
+
+def test_sirt_one_block_one_pass_is_weighted_gradient_step(orc):
+    """With one block the update is x1 = lam V (A^T W b) from x0 = 0, i.e. a
+    step along A^T W b -- checked through the dense matrix."""
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(6, 6, 6), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 8),
+                   dDetector=(1.4, 1.4))
+    ang = synth.circular_angles(5)
+    M = orc.dense_matrix(geo, ang, "siddon")
+    b = np.random.Generator(np.random.PCG64(44)).random(M.shape[0])
+    row = M.sum(1)
+    col = M.sum(0)
+    W = np.where(row > 0, 1 / np.where(row > 0, row, 1), 0)
+    V = np.where(col > 0, 1 / np.where(col > 0, col, 1), 0)
+    want = 0.7 * V * (M.T @ (W * b))
+    got = orc.os_sart(geo, ang, b.reshape((5,) + geo.nDetector), 1, 5, lam=0.7, nonneg=False, kind="siddon")
+    assert _rel(got.ravel(), want) < 1e-12
+
+
+# ------------------------------------------------------------------ PSNR
+def test_psnr_closed_form():
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(45))
+    g = rng.random((4, 5, 6))
+    g[0, 0, 0] = 0.0
+    g[1, 1, 1] = 2.0
+    x = g + 0.01
+    assert abs(oracle.psnr(x, g) - 20 * math.log10(2.0 / 0.01)) < 1e-10
