@@ -1,0 +1,274 @@
+"""Benchmark of the cone-beam projector hot path on one MI355X.
+
+A step is one CGLS iteration on the 512^3 x 720-view workload (1024x768
+detector): q = A p, |q|^2, x/r update with |r|^2, s = A^T r, |s|^2, p update
+-- the forward projector, its exact transpose and the vector updates, with
+every input resident in HBM.  The reported value is A and A^T voxel-view
+updates per second: 2 * N^3 * views / step time.
+
+After the timed steps each operator (Siddon A and A^T, interpolated A and
+A^T, FDK filter, FDK backprojector) is timed on its own for the breakdown,
+and the FP64 CPU oracle is timed on a one-view sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--projector interp|siddon]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# published MI355X peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+# algorithmic FP32 flops per unit of work (add/mul/sub/floor = 1, fma = 2):
+#   interpolated A, per sample: position 3 fma (6), floor 3, fraction 3,
+#     1 - f 3, seven lerps (mul + fma = 3 each) 21, accumulate 1      = 37
+#   interpolated A^T, per sample: position 6, floor 3, fraction 3, 1 - f 3,
+#     eight corner weights (2 mul each) 16, times y 8, accumulate 8    = 47
+#   Siddon A, per segment: 3-way min 2, clip min 1, length sub 1,
+#     accumulate fma 2, exit compare 1, next plane add 1 + fma 2       = 10
+#   Siddon A^T, per segment: the same with one multiply by y           = 11
+#   FDK backprojection, per voxel-view update: v position fma 2, floor 1,
+#     fraction 1, 1 - f 1, two u-lerps 6, v-lerp 3, weight fma 2       = 16
+FLOPS = {"interp_fwd": 37, "interp_bwd": 47, "siddon_fwd": 10, "siddon_bwd": 11, "fdk_bp": 16}
+
+
+def _rays(geo, angles):
+    """Ray end points in voxel-cell coordinates for the listed views (FP64)."""
+    nz, ny, nx = geo.nVoxel
+    dz, dy, dx = geo.dVoxel
+    oz, oy, ox = geo.offOrigin
+    lo = np.array([ox - nx * dx / 2, oy - ny * dy / 2, oz - nz * dz / 2])
+    h = np.array([dx, dy, dz])
+    nv, nu = geo.nDetector
+    iv, iu = np.meshgrid(np.arange(nv), np.arange(nu), indexing="ij")
+    u = (iu + 0.5 - nu / 2) * geo.dDetector[1] + geo.offDetector[1]
+    v = (iv + 0.5 - nv / 2) * geo.dDetector[0] + geo.offDetector[0]
+    for th in angles:
+        c, s = math.cos(th), math.sin(th)
+        S = np.array([geo.DSO * c, geo.DSO * s, 0.0])
+        P = np.stack([S[0] - geo.DSD * c - u * s, S[1] - geo.DSD * s + u * c, v], -1).reshape(-1, 3)
+        yield (S - lo) / h, (P - lo) / h, h
+
+
+def work_units(geo, nviews, sample_views=16):
+    """Interpolation samples and Siddon segments of all rays, counted
+    exactly on `sample_views` evenly spaced views and scaled to all views
+    (work is uniform over the views of a circular orbit)."""
+    n = np.array([geo.nVoxel[2], geo.nVoxel[1], geo.nVoxel[0]], dtype=np.float64)
+    ds = geo.accuracy * min(geo.dVoxel)
+    ang = 2 * np.pi * np.arange(sample_views) / sample_views
+    samples = segments = 0.0
+    for Sc, P, h in _rays(geo, ang):
+        D = P - Sc
+        L = np.linalg.norm(D * h, axis=1)
+        # samples: open box (-1, n) in voxel-centre coordinates, t = k ds
+        st = D * (ds / L)[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ka = (-1.0 - (Sc - 0.5)) / st
+            kb = (n - (Sc - 0.5)) / st
+        kmin = np.maximum(np.nanmax(np.minimum(ka, kb), 1), 0.0)
+        kmax = np.minimum(np.nanmin(np.maximum(ka, kb), 1), L / ds)
+        cnt = np.floor(kmax) - np.ceil(kmin) + 1
+        samples += float(np.sum(np.where(kmax > kmin, np.maximum(cnt, 0), 0)))
+        # segments: cells visited = 1 + planes crossed between entry and exit
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a0 = (0.0 - Sc) / D
+            a1 = (n - Sc) / D
+        amin = np.maximum(np.nanmax(np.minimum(a0, a1), 1), 0.0)
+        amax = np.minimum(np.nanmin(np.maximum(a0, a1), 1), 1.0)
+        hit = amax > amin
+        e = Sc + amin[:, None] * D
+        x = Sc + amax[:, None] * D
+        cross = np.sum(np.abs(np.floor(np.clip(x, 0, n - 1e-9)) - np.floor(np.clip(e, 0, n - 1e-9))), 1)
+        segments += float(np.sum(np.where(hit, cross + 1, 0)))
+    scale = nviews / sample_views
+    return samples * scale, segments * scale
+
+
+def cpu_baseline(geo, angles, x, y, kind):
+    """The FP64 oracle on one view of the workload: forward and backward."""
+    import oracle
+    oracle._L()
+    a1 = angles[:1]
+    x64 = x.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.forward(geo, a1, x64, kind)
+    t1 = time.perf_counter()
+    oracle.backward(geo, a1, y[:1].astype(np.float64), kind)
+    t2 = time.perf_counter()
+    upd = float(np.prod(geo.nVoxel))
+    return {"value": 2 * upd / (t2 - t0), "unit": "voxel-view updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 {kind} A and A^T, 1 of {len(angles)} views of the 512^3 workload "
+                      f"(A {t1 - t0:.1f} s, A^T {t2 - t1:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cbct512")
+    ap.add_argument("--projector", default="interp", choices=["interp", "siddon"])
+    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the view-sharded multi-GPU "
+              "layout is a design only in this repository)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2412_10129_amd as P
+    import synth
+
+    geo, angles = synth.workload(args.workload)
+    nviews = len(angles)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] workload {args.workload}: vol {geo.nVoxel} det {geo.nDetector} views {nviews}", flush=True)
+    x_h = synth.uniform_volume(geo, 4)
+    y_h = synth.uniform_projections(geo, nviews, 5)
+    plan = P.Plan(geo, angles, dev)
+    kind = args.projector
+    x = torch.from_numpy(x_h).to(dev)
+    b = torch.from_numpy(y_h).to(dev)
+    # CGLS state
+    from paper_2412_10129_amd import ops
+    xs = torch.zeros_like(x)
+    r = b.clone()
+    p = x.clone()
+    s = torch.empty_like(x)
+    q = torch.empty_like(b)
+    ws = ops._ws(dev)
+    sc = torch.ones((2, 4), dtype=torch.float64, device=dev)
+    a = sc.data_ptr()
+    stream = torch.cuda.current_stream()
+
+    def dot_into(u, addr):
+        ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(u, "u"), ops._ptr(u, "u"), u.numel(), addr, ws.data_ptr(),
+                                         ws.numel() * 8, ops._stream()))
+
+    ev_f0, ev_f1, ev_b0, ev_b1 = [], [], [], []
+
+    def step(record=False):
+        if record:
+            e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_f0.append(e)
+        plan.forward(p, out=q, kind=kind)
+        if record:
+            e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_f1.append(e)
+        dot_into(q, a + 8)
+        ops.cgls_xr(xs, p, r, q, a, a + 8, a + 16, ws)
+        if record:
+            e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_b0.append(e)
+        plan.backproject(r, out=s, kind=kind)
+        if record:
+            e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_b1.append(e)
+        dot_into(s, a + 24)
+        ops.cgls_p(p, s, a, a + 24)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", flush=True)
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step(record=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    t_fwd = np.mean([a_.elapsed_time(b_) for a_, b_ in zip(ev_f0, ev_f1)])
+    t_bwd = np.mean([a_.elapsed_time(b_) for a_, b_ in zip(ev_b0, ev_b1)])
+    upd = float(np.prod(geo.nVoxel)) * nviews
+    value = 2 * upd / (ms / 1e3)
+    print(f"[bench] {args.steps} steps: {ms:.2f} ms/step (wall {wall:.2f} s); A {t_fwd:.2f} ms, A^T {t_bwd:.2f} ms",
+          flush=True)
+
+    samples, segments = work_units(geo, nviews)
+    units = {"interp_fwd": samples, "interp_bwd": samples, "siddon_fwd": segments, "siddon_bwd": segments}
+    kf, kb = f"{kind}_fwd", f"{kind}_bwd"
+    dominant, t_dom = (kb, t_bwd) if t_bwd >= t_fwd else (kf, t_fwd)
+    fl = FLOPS[dominant] * units[dominant]
+    ach = fl / (t_dom / 1e3) / 1e12
+    roofline = {"bound": "alu", "kernel": dominant, "achieved": round(ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "work_units": units[dominant], "flops_per_unit": FLOPS[dominant],
+                "avg_launch_ms": round(float(t_dom), 3)}
+
+    breakdown = {}
+    if not args.no_breakdown:
+        fl_fdk = float(np.prod(geo.nVoxel)) * nviews
+        ops_list = [
+            ("siddon_fwd", lambda: plan.forward(x, out=q, kind="siddon")),
+            ("siddon_bwd", lambda: plan.backproject(b, out=s, kind="siddon")),
+            ("interp_fwd", lambda: plan.forward(x, out=q, kind="interp")),
+            ("interp_bwd", lambda: plan.backproject(b, out=s, kind="interp")),
+            ("fdk_filter", lambda: plan.fdk_filter(b, out=q)),
+            ("fdk_bp", lambda: plan.backproject(b, out=s, kind="fdk")),
+        ]
+        for name, fn in ops_list:
+            fn()
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(stream)
+            for _ in range(2):
+                fn()
+            eb.record(stream)
+            torch.cuda.synchronize()
+            t = ea.elapsed_time(eb) / 2
+            ent = {"ms": round(t, 3)}
+            if name == "fdk_filter":
+                ent["GB/s"] = round(2 * 4 * b.numel() / (t / 1e3) / 1e9, 1)
+            else:
+                ent["updates/s"] = float(f"{upd / (t / 1e3):.4g}")
+                u = units.get(name, fl_fdk)
+                ent["TFLOP/s"] = round(FLOPS[name] * u / (t / 1e3) / 1e12, 3)
+            breakdown[name] = ent
+            print(f"[bench] {name}: {ent}", flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on one view ...", flush=True)
+        cpu = cpu_baseline(geo, angles, x_h, y_h, kind)
+
+    out = {
+        "metric": "A/A^T voxel-view updates/s at 512^3 x 720",
+        "value": float(f"{value:.4g}"),
+        "unit": "voxel-view updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded U(0,1) volume and projections)",
+        "config": {"workload": args.workload, "volume": list(geo.nVoxel), "views": nviews,
+                   "detector": list(geo.nDetector), "projector": kind,
+                   "step": "CGLS iteration: A, |q|^2, x/r update, A^T, |s|^2, p update"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "breakdown": breakdown,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * ctmi -- cone-beam CT projectors and reconstruction updates for MI355X (gfx950).
+ *
+ * C ABI of libctmi.so.  The operations are those of the iterative cone-beam
+ * reconstruction hot path described in TIGRE v3 (arXiv 2412.10129): the
+ * forward projector A and its adjoint of the linear model A x + e = b
+ * (section 2.1, Eq. 1), the FDK direct method with its filter and weights
+ * (section 2.1, direct methods), the CGLS Krylov updates (section 2.1 list of
+ * Krylov methods; section 2.2.1) and the ordered-subset SART step (section
+ * 2.2.2, Eq. 6), in the circular cone-beam geometry of section 2.4 and the
+ * geometry table of the appendix on geometric parameters.
+ *
+ * Conventions, shared by every call:
+ *   - world frame Oxyz in mm; the object is static; the source rotates about
+ *     +z: S = DSO (cos t, sin t, 0); detector centre S - DSD (cos t, sin t, 0);
+ *     detector axes u = (-sin t, cos t, 0), v = (0, 0, 1); pixel (iv, iu)
+ *     centre at u = (iu + 1/2 - nu/2) du + offDetector[1],
+ *                  v = (iv + 1/2 - nv/2) dv + offDetector[0];
+ *   - voxel (iz, iy, ix) is the cell [lo + i d, lo + (i+1) d) per axis with
+ *     lo = offOrigin - n d / 2;
+ *   - volumes are float32 C-order [nz][ny][nx] (x fastest); projections are
+ *     float32 C-order [nviews][nv][nu] (u fastest);
+ *   - every per-axis array of the volume is ordered (z, y, x), every
+ *     per-axis array of the detector (v, u).
+ *
+ * Memory and streams: all array arguments are DEVICE pointers, 4-byte
+ * aligned, owned by the caller.  The library never allocates or frees per
+ * call and keeps no pointer after a call returns.  Every call is
+ * asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
+ * returns after enqueueing its kernels.  A plan owns a small device table
+ * (per-view geometry and filter coefficients) allocated on the device that
+ * is current when the plan is created; calls must run with that device
+ * current.
+ *
+ * Errors: every call returns CTMI_OK (0) or a negative code; argument checks
+ * happen before anything is enqueued, so a failing call has no effect.
+ * ctmi_last_error() returns a thread-local message for the last failure.
+ * Faults inside kernels surface asynchronously through the HIP runtime.
+ */
+#ifndef CTMI_H
+#define CTMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CTMI_OK = 0,
+    CTMI_EINVAL = -1,       /* bad geometry, pointer, range or size */
+    CTMI_EUNSUPPORTED = -2, /* a geometry feature this build does not model */
+    CTMI_EOVERFLOW = -3,    /* sizes beyond the library's index range */
+    CTMI_EWORKSPACE = -4,   /* workspace missing or too small */
+    CTMI_EHIP = -5          /* the HIP runtime reported an error */
+};
+
+/* Projector models of A (the paper's linear model, section 2.1). */
+enum ctmi_projector {
+    CTMI_SIDDON = 0, /* exact radiological path: length of ray i in voxel j (Siddon 1985) */
+    CTMI_INTERP = 1  /* trilinear ray marching, samples t_k = k ds from the source */
+};
+
+/* Backprojectors. */
+enum ctmi_backprojector {
+    CTMI_BP_SIDDON = 0, /* exact transpose of CTMI_SIDDON */
+    CTMI_BP_INTERP = 1, /* exact transpose of CTMI_INTERP */
+    CTMI_BP_FDK = 2     /* FDK backprojector: sum_views (DSO/U)^2 bilinear(q; u, v) */
+};
+
+/* Geometry parameters (the paper's geometry-parameter table).  The table's
+ * total sizes sVoxel / sDetector are n * d and are not passed.  COR and
+ * rotDetector must be 0 and accuracy > 0 (default 0.5 voxel). */
+typedef struct {
+    double DSD;            /* source -> detector distance, mm */
+    double DSO;            /* source -> origin distance, mm */
+    int64_t nVoxel[3];     /* (nz, ny, nx) */
+    double dVoxel[3];      /* (dz, dy, dx) mm */
+    double offOrigin[3];   /* (z, y, x) mm: volume centre */
+    int64_t nDetector[2];  /* (nv, nu) */
+    double dDetector[2];   /* (dv, du) mm */
+    double offDetector[2]; /* (v, u) mm */
+    double COR;            /* centre-of-rotation shift, must be 0 */
+    double rotDetector[3]; /* detector in-place rotation, must be 0 */
+    double accuracy;       /* interpolated-projector step in voxels (min voxel size) */
+} ctmi_geometry;
+
+typedef struct ctmi_plan ctmi_plan;
+
+/* Thread-local description of the last error (never NULL). */
+const char* ctmi_last_error(void);
+
+/* Library version string. */
+const char* ctmi_version(void);
+
+/* Validate a geometry without touching the GPU.  Checks: positive sizes and
+ * spacings, DSD > DSO, the volume's circumscribed sphere (grown by one voxel)
+ * strictly between the source and the detector plane, finite angles,
+ * nvox < 2^31.  Returns CTMI_OK, CTMI_EINVAL, CTMI_EUNSUPPORTED or
+ * CTMI_EOVERFLOW.  `angles` is a HOST array of nviews z1 angles (rad). */
+int ctmi_geometry_check(const ctmi_geometry* geo, const double* angles, int64_t nviews);
+
+/* Per-view geometry as used on the device (host copy, for inspection):
+ * writes 32 floats per view into `out` (host memory, 32 * nviews floats).
+ * Layout: [0:3] source, [3:6] centre of pixel (0,0), [6:9] step per iu,
+ * [9:12] step per iv, all in voxel-cell coordinates (volume corner at 0,
+ * one unit per voxel); [12:16], [16:20], [20:24] the rows of the 3x4 matrix
+ * taking voxel-centre indices (ix, iy, iz, 1) to (fu W, fv W, W), W = U/DSO,
+ * (fu, fv) pixel-index coordinates.  No GPU needed. */
+int ctmi_view_table(const ctmi_geometry* geo, const double* angles, int64_t nviews, float* out);
+
+/* Create a plan for `nviews` views (angles: HOST array, z1 angles in rad).
+ * Validates as ctmi_geometry_check, computes the per-view table in FP64 and
+ * uploads it in FP32 to the current device (synchronous).  *out is set on
+ * success only. */
+int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nviews, ctmi_plan** out);
+
+/* Destroy a plan; waits for the device, then frees the plan's table.  No
+ * call using the plan may be in flight.  NULL is accepted. */
+int ctmi_plan_destroy(ctmi_plan* plan);
+
+/* proj = A vol for views [view0, view0 + nviews) of the plan.
+ * vol: [nz][ny][nx]; proj: [nviews][nv][nu] holding only those views.
+ * projector: CTMI_SIDDON or CTMI_INTERP.  Overwrites proj.
+ * (Section 2.1, Eq. 1: the line integrals of the discretised image.) */
+int ctmi_forward(const ctmi_plan* plan, int projector, const float* vol, float* proj, int64_t view0,
+                 int64_t nviews, void* stream);
+
+/* vol = beta * vol + B proj for views [view0, view0 + nviews).
+ * bp = CTMI_BP_SIDDON / CTMI_BP_INTERP: B is the exact transpose A^T of the
+ * matching projector (the adjoint the Krylov methods of section 2.2.1
+ * require), computed brick-by-brick with one writer per voxel.
+ * bp = CTMI_BP_FDK: B is the FDK backprojector (DSO/U)^2-weighted bilinear
+ * detector sampling (section 2.1, FDK).  beta = 0 ignores the old contents
+ * of vol (NaNs included). */
+int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0,
+                     int64_t nviews, float beta, void* stream);
+
+/* FDK filtering of views [view0, view0 + nviews): out = scale * tau *
+ * (h * (w_cos * w_wang * proj)) row by row, h the Ram-Lak kernel on the iso
+ * grid tau = du DSO / DSD (h[0] = 1/(4 tau^2), h[odd n] = -1/(n^2 pi^2 tau^2)),
+ * applied as a linear convolution (zero-padded FFT), w_cos = DSD /
+ * sqrt(DSD^2 + u^2 + v^2), w_wang the Wang offset-detector weight when
+ * `wang` is nonzero, scale = pi / N (wang = 0) or 2 pi / N (wang != 0), N the
+ * plan's view count.  proj and out may alias.  (Section 2.1, direct
+ * methods: FDK with filters and Wang weights.) */
+int ctmi_fdk_filter(const ctmi_plan* plan, int wang, const float* proj, float* out, int64_t view0,
+                    int64_t nviews, void* stream);
+
+/* ------------------------------------------------------------ vectors -- */
+/* Workspace (device, bytes) needed by the reductions for n elements. */
+size_t ctmi_reduce_workspace_bytes(int64_t n);
+
+/* *out = sum_i a[i] * b[i], accumulated in FP64, deterministic (fixed
+ * blocking and order).  out: one device double.  ws: device workspace of at
+ * least ctmi_reduce_workspace_bytes(n) bytes.  a and b may alias. */
+int ctmi_dot(const float* a, const float* b, int64_t n, double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* y = a * x + b * y (float scalars). */
+int ctmi_axpby(int64_t n, float a, const float* x, float b, float* y, void* stream);
+
+/* CGLS step (Hestenes-Stiefel, section 2.2.1): alpha = gamma / delta read
+ * from device doubles (alpha = 0 when delta == 0); x += alpha p (nvol
+ * elements); r -= alpha q (nproj elements); then *rnorm2 = |r|^2 in FP64.
+ * ws: ctmi_reduce_workspace_bytes(nproj) bytes. */
+int ctmi_cgls_xr(float* x, const float* p, int64_t nvol, float* r, const float* q, int64_t nproj,
+                 const double* gamma, const double* delta, double* rnorm2, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* CGLS direction: beta = gamma_new / gamma_old (device doubles; 0 when
+ * gamma_old == 0); p = s + beta p. */
+int ctmi_cgls_p(float* p, const float* s, int64_t n, const double* gamma_old, const double* gamma_new,
+                void* stream);
+
+/* SART weights: out[i] = 1 / in[i], or 0 where in[i] == 0 (the row / column
+ * sums W = 1/(A 1), V = 1/(A^T 1)).  in and out may alias. */
+int ctmi_recip_or_zero(const float* in, float* out, int64_t n, void* stream);
+
+/* SART residual: out = w * (b - ax).  out may alias ax. */
+int ctmi_sart_residual(const float* b, const float* ax, const float* w, float* out, int64_t n, void* stream);
+
+/* SART update (section 2.2.2, Eq. 6 with the descent sign): x = x + lam * v *
+ * bp, then x = max(x, 0) when nonneg != 0. */
+int ctmi_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg,
+                     void* stream);
+
+/* Squared error inside the field of view (section 2.2.3 ground-truth error
+ * history): out[0] = sum (x - gt)^2 and out[1] = voxel count, over voxels
+ * whose centre lies inside the volume's inscribed cylinder, FP64.
+ * ws: ctmi_reduce_workspace_bytes(nvox) bytes. */
+int ctmi_fov_sq_err(const ctmi_plan* plan, const float* x, const float* gt, double* out, void* ws,
+                    size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTMI_H */

@@ -1,0 +1,19 @@
+"""MI355X-native cone-beam CT projectors (TIGRE v3, arXiv 2412.10129):
+Siddon and interpolated forward projectors, their exact transposes, FDK,
+CGLS and OS-SART on hand-written HIP kernels for gfx950 (libctmi.so)."""
+from . import _lib
+from ._lib import CtmiError
+from .ops import Plan, geometry_check, view_table, dot, axpby
+from .algs import fdk, cgls, os_sart, OSSART, psnr_from_sq_err
+from .projector import Projector, create_pytorch_operator
+
+__all__ = ["Plan", "geometry_check", "view_table", "dot", "axpby", "fdk", "cgls", "os_sart", "OSSART",
+           "psnr_from_sq_err", "Projector", "create_pytorch_operator", "CtmiError"]
+
+
+def library():
+    """The loaded libctmi (raises ImportError if it is not built)."""
+    return _lib.lib()
+
+
+library()

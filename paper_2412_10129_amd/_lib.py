@@ -1,0 +1,99 @@
+"""ctypes binding of libctmi.so: argument marshalling only.
+
+Every computation happens in the HIP library.  If the library is missing the
+import fails loudly; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctmi.so")
+
+CTMI_OK, CTMI_EINVAL, CTMI_EUNSUPPORTED, CTMI_EOVERFLOW, CTMI_EWORKSPACE, CTMI_EHIP = 0, -1, -2, -3, -4, -5
+CTMI_SIDDON, CTMI_INTERP = 0, 1
+CTMI_BP_SIDDON, CTMI_BP_INTERP, CTMI_BP_FDK = 0, 1, 2
+
+c_i64, c_f, c_d, c_p, c_int = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+
+
+class CtmiGeometry(ctypes.Structure):
+    _fields_ = [("DSD", c_d), ("DSO", c_d), ("nVoxel", c_i64 * 3), ("dVoxel", c_d * 3), ("offOrigin", c_d * 3),
+                ("nDetector", c_i64 * 2), ("dDetector", c_d * 2), ("offDetector", c_d * 2), ("COR", c_d),
+                ("rotDetector", c_d * 3), ("accuracy", c_d)]
+
+
+def geometry_struct(geo) -> CtmiGeometry:
+    """From any object with the geometry-table attributes (DSD, DSO, nVoxel,
+    dVoxel, nDetector, dDetector and optionally offOrigin, offDetector, COR,
+    rotDetector, accuracy)."""
+    g = CtmiGeometry()
+    g.DSD = float(geo.DSD)
+    g.DSO = float(geo.DSO)
+    g.nVoxel = (c_i64 * 3)(*[int(v) for v in geo.nVoxel])
+    g.dVoxel = (c_d * 3)(*[float(v) for v in geo.dVoxel])
+    g.offOrigin = (c_d * 3)(*[float(v) for v in getattr(geo, "offOrigin", (0.0, 0.0, 0.0))])
+    g.nDetector = (c_i64 * 2)(*[int(v) for v in geo.nDetector])
+    g.dDetector = (c_d * 2)(*[float(v) for v in geo.dDetector])
+    g.offDetector = (c_d * 2)(*[float(v) for v in getattr(geo, "offDetector", (0.0, 0.0))])
+    g.COR = float(getattr(geo, "COR", 0.0))
+    g.rotDetector = (c_d * 3)(*[float(v) for v in getattr(geo, "rotDetector", (0.0, 0.0, 0.0))])
+    g.accuracy = float(getattr(geo, "accuracy", 0.5))
+    return g
+
+
+_SIGS = {
+    "ctmi_last_error": (ctypes.c_char_p, []),
+    "ctmi_version": (ctypes.c_char_p, []),
+    "ctmi_geometry_check": (c_int, [c_p, c_p, c_i64]),
+    "ctmi_view_table": (c_int, [c_p, c_p, c_i64, c_p]),
+    "ctmi_plan_create": (c_int, [c_p, c_p, c_i64, ctypes.POINTER(c_p)]),
+    "ctmi_plan_destroy": (c_int, [c_p]),
+    "ctmi_forward": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),
+    "ctmi_backproject": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_f, c_p]),
+    "ctmi_fdk_filter": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),
+    "ctmi_reduce_workspace_bytes": (ctypes.c_size_t, [c_i64]),
+    "ctmi_dot": (c_int, [c_p, c_p, c_i64, c_p, c_p, ctypes.c_size_t, c_p]),
+    "ctmi_axpby": (c_int, [c_i64, c_f, c_p, c_f, c_p, c_p]),
+    "ctmi_cgls_xr": (c_int, [c_p, c_p, c_i64, c_p, c_p, c_i64, c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
+    "ctmi_cgls_p": (c_int, [c_p, c_p, c_i64, c_p, c_p, c_p]),
+    "ctmi_recip_or_zero": (c_int, [c_p, c_p, c_i64, c_p]),
+    "ctmi_sart_residual": (c_int, [c_p, c_p, c_p, c_p, c_i64, c_p]),
+    "ctmi_sart_update": (c_int, [c_p, c_p, c_p, c_i64, c_f, c_int, c_p]),
+    "ctmi_fov_sq_err": (c_int, [c_p, c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+class CtmiError(RuntimeError):
+    pass
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2412_10129_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc == CTMI_OK:
+        return
+    msg = lib().ctmi_last_error().decode()
+    if rc == CTMI_EINVAL:
+        raise ValueError(msg)
+    if rc == CTMI_EUNSUPPORTED:
+        raise NotImplementedError(msg)
+    raise CtmiError(f"ctmi error {rc}: {msg}")

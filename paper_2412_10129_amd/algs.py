@@ -1,0 +1,138 @@
+"""Reconstruction drivers over libctmi kernels: FDK, CGLS and OS-SART.
+
+The loops are host-side sequencing only; every arithmetic step is a libctmi
+kernel, and the iteration scalars (norms, alpha, beta) stay on the device so
+a loop never waits for the host.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import ops
+from .ops import Plan
+
+
+def fdk(plan: Plan, proj: torch.Tensor, wang: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """FDK (section 2.1, direct methods): weight and ramp-filter each row,
+    then the (DSO/U)^2-weighted voxel-driven backprojection."""
+    q = plan.fdk_filter(proj, wang=wang)
+    return plan.backproject(q, out=out, kind="fdk")
+
+
+def _addr(t: torch.Tensor, i: int, j: int) -> int:
+    return t.data_ptr() + 8 * (i * t.shape[1] + j)
+
+
+def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Optional[torch.Tensor] = None,
+         x0: Optional[torch.Tensor] = None, sync: bool = True):
+    """CGLS (Hestenes-Stiefel; the Krylov solvers of section 2.2.1).
+
+    x0 = 0 (or the given start); r = b - A x0; s = A^T r; p = s; gamma = |s|^2;
+    per iteration q = A p, delta = |q|^2, alpha = gamma/delta, x += alpha p,
+    r -= alpha q, s = A^T r, gamma' = |s|^2, beta = gamma'/gamma, p = s + beta p.
+
+    Returns (x, hist): hist holds per-iteration gamma, delta, |r|^2 and, given
+    x_gt, the squared error and voxel count inside the FOV (the residual and
+    error-norm histories of section 2.2.3).  With sync=False, hist holds the
+    device tensors instead of host arrays.
+    """
+    dev = plan.device
+    vol_shape, proj_shape = plan.vol_shape, plan.proj_shape()
+    ws = ops._ws(dev)
+    sc = torch.zeros((niter + 1, 3), dtype=torch.float64, device=dev)   # gamma_k, delta_k, |r_k|^2
+    err = torch.zeros((niter, 2), dtype=torch.float64, device=dev)
+    if x0 is None:
+        x = torch.zeros(vol_shape, dtype=torch.float32, device=dev)
+        r = b.clone()
+    else:
+        x = x0.clone()
+        r = plan.forward(x, kind=kind)
+        ops.axpby(1.0, b, -1.0, r)
+    s = plan.backproject(r, kind=kind)
+    p = s.clone()
+    q = torch.empty(proj_shape, dtype=torch.float32, device=dev)
+    ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(s, "s"), ops._ptr(s, "s"), s.numel(), _addr(sc, 0, 0),
+                                     ws.data_ptr(), ws.numel() * 8, ops._stream()))
+    for k in range(niter):
+        plan.forward(p, out=q, kind=kind)
+        ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(q, "q"), ops._ptr(q, "q"), q.numel(), _addr(sc, k, 1),
+                                         ws.data_ptr(), ws.numel() * 8, ops._stream()))
+        ops.cgls_xr(x, p, r, q, _addr(sc, k, 0), _addr(sc, k, 1), _addr(sc, k, 2), ws)
+        plan.backproject(r, out=s, kind=kind)
+        ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(s, "s"), ops._ptr(s, "s"), s.numel(), _addr(sc, k + 1, 0),
+                                         ws.data_ptr(), ws.numel() * 8, ops._stream()))
+        ops.cgls_p(p, s, _addr(sc, k, 0), _addr(sc, k + 1, 0))
+        if x_gt is not None:
+            plan.fov_sq_err(x, x_gt, err[k])
+    hist = {"scalars": sc, "err": err}
+    if sync:
+        h = sc.cpu().numpy()
+        hist = {"gamma": h[:, 0], "delta": h[:niter, 1], "resid": np.sqrt(h[:niter, 2]),
+                "alpha": h[:niter, 0] / np.where(h[:niter, 1] != 0, h[:niter, 1], np.inf),
+                "beta": h[1:, 0] / np.where(h[:niter, 0] != 0, h[:niter, 0], np.inf)}
+        stop = np.nonzero((h[:niter, 1] == 0) | (h[:niter, 0] == 0))[0]
+        hist["stopped"] = int(stop[0]) if len(stop) else None
+        if x_gt is not None:
+            e = err.cpu().numpy()
+            hist["sq_err"] = e[:, 0]
+            hist["count"] = e[:, 1]
+    return x, hist
+
+
+def psnr_from_sq_err(sq_err, count, data_range: float):
+    """PSNR = 10 log10(R^2 / MSE) over the FOV (section 2.2.3 error history)."""
+    sq_err = np.asarray(sq_err, dtype=np.float64)
+    mse = sq_err / np.asarray(count, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return 10.0 * np.log10(data_range * data_range / mse)
+
+
+def subsets(nviews: int, blocksize: int):
+    """Consecutive blocks of views visited in order (section 2.2.2)."""
+    return [(s, min(blocksize, nviews - s)) for s in range(0, nviews, blocksize)]
+
+
+class OSSART:
+    """OS-SART (section 2.2.2, Eq. 6 with the descent sign; SART row/column
+    normalisation).  SART is blocksize 1, SIRT one block of all views.
+
+    Precomputes W = 1/(A 1) for all views (one projection-sized array) and
+    V_s = 1/(A_s^T 1) per block (one volume per block)."""
+
+    def __init__(self, plan: Plan, blocksize: int, kind: str = "interp"):
+        self.plan, self.kind = plan, kind
+        self.blocks = subsets(plan.nviews, blocksize)
+        dev = plan.device
+        ones_v = torch.ones(plan.vol_shape, dtype=torch.float32, device=dev)
+        self.W = plan.forward(ones_v, kind=kind)
+        ops.recip_or_zero(self.W)
+        self.V = []
+        for v0, nb in self.blocks:
+            ones_p = torch.ones(plan.proj_shape(nb), dtype=torch.float32, device=dev)
+            V = plan.backproject(ones_p, kind=kind, view0=v0, nviews=nb)
+            self.V.append(ops.recip_or_zero(V))
+        mb = max(nb for _, nb in self.blocks)
+        self._e = torch.empty(plan.proj_shape(mb), dtype=torch.float32, device=dev)
+        self._bp = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+
+    def run(self, b: torch.Tensor, niter: int, lam: float = 1.0, nonneg: bool = True,
+            x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        plan = self.plan
+        x = torch.zeros(plan.vol_shape, dtype=torch.float32, device=plan.device) if x0 is None else x0.clone()
+        for _ in range(niter):
+            for s, (v0, nb) in enumerate(self.blocks):
+                e = self._e[:nb]
+                plan.forward(x, out=e, kind=self.kind, view0=v0, nviews=nb)
+                ops.sart_residual(b[v0:v0 + nb], e, self.W[v0:v0 + nb], e)
+                plan.backproject(e, out=self._bp, kind=self.kind, view0=v0, nviews=nb)
+                ops.sart_update(x, self.V[s], self._bp, lam, nonneg)
+        return x
+
+
+def os_sart(plan: Plan, b: torch.Tensor, niter: int, blocksize: int, lam: float = 1.0, nonneg: bool = True,
+            kind: str = "interp", x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+    return OSSART(plan, blocksize, kind).run(b, niter, lam, nonneg, x0)

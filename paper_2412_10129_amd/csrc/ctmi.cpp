@@ -1,0 +1,451 @@
+// Host side of libctmi: argument validation, the FP64 per-view geometry
+// plan, the FFT filter tables and the exported C entry points.  Every check
+// runs before anything is enqueued, so a failing call has no side effect.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ctmi_internal.h"
+
+namespace ctmi {
+size_t reduce_ws_bytes();
+}
+
+using ctmi::Plan;
+using ctmi::ViewGeo;
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(CTMI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_geometry(const ctmi_geometry* g, const double* angles, int64_t nviews)
+{
+    if (!g) return fail(CTMI_EINVAL, "geometry is NULL");
+    if (nviews < 1) return fail(CTMI_EINVAL, "nviews must be >= 1 (got %lld)", (long long)nviews);
+    if (!angles) return fail(CTMI_EINVAL, "angles is NULL");
+    if (!finite_pos(g->DSO) || !finite_pos(g->DSD)) return fail(CTMI_EINVAL, "DSO and DSD must be finite and > 0");
+    if (!(g->DSD > g->DSO)) return fail(CTMI_EINVAL, "DSD must exceed DSO");
+    for (int a = 0; a < 3; ++a) {
+        if (g->nVoxel[a] < 1) return fail(CTMI_EINVAL, "nVoxel[%d] must be >= 1", a);
+        if (!finite_pos(g->dVoxel[a])) return fail(CTMI_EINVAL, "dVoxel[%d] must be finite and > 0", a);
+        if (!std::isfinite(g->offOrigin[a])) return fail(CTMI_EINVAL, "offOrigin[%d] is not finite", a);
+        if (!std::isfinite(g->rotDetector[a])) return fail(CTMI_EINVAL, "rotDetector[%d] is not finite", a);
+    }
+    for (int a = 0; a < 2; ++a) {
+        if (g->nDetector[a] < 1) return fail(CTMI_EINVAL, "nDetector[%d] must be >= 1", a);
+        if (!finite_pos(g->dDetector[a])) return fail(CTMI_EINVAL, "dDetector[%d] must be finite and > 0", a);
+        if (!std::isfinite(g->offDetector[a])) return fail(CTMI_EINVAL, "offDetector[%d] is not finite", a);
+    }
+    if (!finite_pos(g->accuracy)) return fail(CTMI_EINVAL, "accuracy must be finite and > 0");
+    if (!std::isfinite(g->COR)) return fail(CTMI_EINVAL, "COR is not finite");
+    for (int64_t k = 0; k < nviews; ++k)
+        if (!std::isfinite(angles[k])) return fail(CTMI_EINVAL, "angle %lld is not finite", (long long)k);
+    if (g->COR != 0.0) return fail(CTMI_EUNSUPPORTED, "COR != 0 is not modelled by this build");
+    if (g->rotDetector[0] != 0.0 || g->rotDetector[1] != 0.0 || g->rotDetector[2] != 0.0)
+        return fail(CTMI_EUNSUPPORTED, "rotDetector != 0 is not modelled by this build");
+    const int64_t nz = g->nVoxel[0], ny = g->nVoxel[1], nx = g->nVoxel[2];
+    if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return fail(CTMI_EOVERFLOW, "volume dimension too large");
+    if ((double)nx * ny * nz >= 2147483648.0) return fail(CTMI_EOVERFLOW, "volume must hold < 2^31 voxels");
+    const int64_t nv = g->nDetector[0], nu = g->nDetector[1];
+    if (nu > 4096 || nv > (1 << 20)) return fail(CTMI_EOVERFLOW, "detector must have nu <= 4096");
+    if (nviews > (1 << 24)) return fail(CTMI_EOVERFLOW, "too many views");
+    // the volume's circumscribed sphere, grown by one voxel, must lie strictly
+    // between the source and the detector plane for every view
+    double half2 = 0.0, off2 = 0.0, dmax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double h = 0.5 * (double)g->nVoxel[a] * g->dVoxel[a] + g->dVoxel[a];
+        half2 += h * h;
+        off2 += g->offOrigin[a] * g->offOrigin[a];
+        dmax = std::fmax(dmax, g->dVoxel[a]);
+    }
+    const double R = std::sqrt(half2) + std::sqrt(off2);
+    if (!(g->DSO > R)) return fail(CTMI_EINVAL, "the source passes within the volume (DSO %.6g <= radius %.6g)", g->DSO, R);
+    if (!(g->DSD - g->DSO > R))
+        return fail(CTMI_EINVAL, "the detector cuts the volume (DSD - DSO %.6g <= radius %.6g)", g->DSD - g->DSO, R);
+    return CTMI_OK;
+}
+
+// Per-view table in FP64, rounded once to FP32.
+void view_table(const ctmi_geometry* g, const double* angles, int64_t nviews, ViewGeo* out)
+{
+    const double nz = (double)g->nVoxel[0], ny = (double)g->nVoxel[1], nx = (double)g->nVoxel[2];
+    const double hz = g->dVoxel[0], hy = g->dVoxel[1], hx = g->dVoxel[2];
+    const double lo[3] = {g->offOrigin[2] - 0.5 * nx * hx, g->offOrigin[1] - 0.5 * ny * hy,
+                          g->offOrigin[0] - 0.5 * nz * hz};
+    const double h[3] = {hx, hy, hz};
+    const double nu = (double)g->nDetector[1], nv = (double)g->nDetector[0];
+    const double du = g->dDetector[1], dv = g->dDetector[0];
+    const double ou = g->offDetector[1], ov = g->offDetector[0];
+    const double u0 = (0.5 - 0.5 * nu) * du + ou, v0 = (0.5 - 0.5 * nv) * dv + ov;
+    const double DSO = g->DSO, DSD = g->DSD;
+    for (int64_t k = 0; k < nviews; ++k) {
+        const double c = std::cos(angles[k]), s = std::sin(angles[k]);
+        const double S[3] = {DSO * c, DSO * s, 0.0};
+        const double P00[3] = {S[0] - DSD * c - u0 * s, S[1] - DSD * s + u0 * c, v0};
+        const double DU[3] = {-du * s, du * c, 0.0};
+        const double DV[3] = {0.0, 0.0, dv};
+        ViewGeo& o = out[k];
+        std::memset(&o, 0, sizeof o);
+        for (int a = 0; a < 3; ++a) {
+            o.S[a] = (float)((S[a] - lo[a]) / h[a]);
+            o.P00[a] = (float)((P00[a] - lo[a]) / h[a]);
+            o.DU[a] = (float)(DU[a] / h[a]);
+            o.DV[a] = (float)(DV[a] / h[a]);
+        }
+        // world position of voxel centre index c: X = lo + (c + 1/2) h
+        const double X0 = lo[0] + 0.5 * hx, Y0 = lo[1] + 0.5 * hy, Z0 = lo[2] + 0.5 * hz;
+        // W = U / DSO = 1 - (X c + Y s) / DSO
+        const double MW[4] = {-hx * c / DSO, -hy * s / DSO, 0.0, 1.0 - (X0 * c + Y0 * s) / DSO};
+        // fu W = (DSD/DSO (-X s + Y c) - ou W) / du + (nu/2 - 1/2) W
+        const double ku = 0.5 * nu - 0.5 - ou / du, kv = 0.5 * nv - 0.5 - ov / dv;
+        const double mag = DSD / DSO;
+        const double MU[4] = {mag * (-s * hx) / du + ku * MW[0], mag * (c * hy) / du + ku * MW[1], 0.0,
+                              mag * (-s * X0 + c * Y0) / du + ku * MW[3]};
+        // fv W = (DSD/DSO Z - ov W) / dv + (nv/2 - 1/2) W
+        const double MV[4] = {kv * MW[0], kv * MW[1], mag * hz / dv, mag * Z0 / dv + kv * MW[3]};
+        for (int a = 0; a < 4; ++a) {
+            o.MU[a] = (float)MU[a];
+            o.MV[a] = (float)MV[a];
+            o.MW[a] = (float)MW[a];
+        }
+    }
+}
+
+int bitrev(int x, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+// Frequency response of the zero-padded Ram-Lak kernel on the iso grid
+// tau = du DSO / DSD: H[k] = tau (h[0] + 2 sum_{n odd < nu} h[n] cos(2 pi k n / L)),
+// times 1/L for the inverse transform, stored in bit-reversed order.
+void ramp_tables(const ctmi_geometry* g, int L, int logL, std::vector<float>& Hbr, std::vector<float>& tw)
+{
+    const int64_t nu = g->nDetector[1];
+    const double tau = g->dDetector[1] * g->DSO / g->DSD;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> H(L);
+    for (int k = 0; k < L; ++k) {
+        double acc = 1.0 / (4.0 * tau * tau);
+        for (int64_t n = 1; n < nu; n += 2)
+            acc += 2.0 * (-1.0 / ((double)n * n * pi * pi * tau * tau)) * std::cos(2.0 * pi * (double)k * n / L);
+        H[k] = tau * acc / (double)L;
+    }
+    Hbr.resize(L);
+    for (int k = 0; k < L; ++k) Hbr[k] = (float)H[bitrev(k, logL)];
+    tw.resize(L);  // L/2 complex values
+    for (int k = 0; k < L / 2; ++k) {
+        tw[2 * k] = (float)std::cos(-2.0 * pi * k / L);
+        tw[2 * k + 1] = (float)std::sin(-2.0 * pi * k / L);
+    }
+}
+
+int check_plan(const ctmi_plan* p)
+{
+    if (!p) return fail(CTMI_EINVAL, "plan is NULL");
+    return CTMI_OK;
+}
+
+int check_views(const Plan* p, int64_t view0, int64_t nviews)
+{
+    if (view0 < 0 || nviews < 0 || view0 > p->nviews || nviews > p->nviews - view0)
+        return fail(CTMI_EINVAL, "view range [%lld, %lld) outside the plan's %lld views", (long long)view0,
+                    (long long)(view0 + nviews), (long long)p->nviews);
+    return CTMI_OK;
+}
+
+int check_ptr(const void* ptr, const char* name)
+{
+    if (!ptr) return fail(CTMI_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(ptr) % 4 != 0) return fail(CTMI_EINVAL, "%s is not 4-byte aligned", name);
+    return CTMI_OK;
+}
+
+int check_device(const Plan* p)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != p->device) return fail(CTMI_EINVAL, "plan was created on device %d but device %d is current", p->device, dev);
+    return CTMI_OK;
+}
+
+int launched(hipError_t e, const char* what) { return e == hipSuccess ? CTMI_OK : hip_fail(e, what); }
+
+}  // namespace
+
+struct ctmi_plan : Plan {};
+
+extern "C" {
+
+const char* ctmi_last_error(void) { return g_err; }
+
+const char* ctmi_version(void) { return "ctmi 0.1 (gfx950)"; }
+
+int ctmi_geometry_check(const ctmi_geometry* geo, const double* angles, int64_t nviews)
+{
+    return check_geometry(geo, angles, nviews);
+}
+
+int ctmi_view_table(const ctmi_geometry* geo, const double* angles, int64_t nviews, float* out)
+{
+    int rc = check_geometry(geo, angles, nviews);
+    if (rc) return rc;
+    if (!out) return fail(CTMI_EINVAL, "out is NULL");
+    std::vector<ViewGeo> t(nviews);
+    view_table(geo, angles, nviews, t.data());
+    std::memcpy(out, t.data(), sizeof(ViewGeo) * (size_t)nviews);
+    return CTMI_OK;
+}
+
+int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nviews, ctmi_plan** out)
+{
+    if (!out) return fail(CTMI_EINVAL, "out is NULL");
+    int rc = check_geometry(geo, angles, nviews);
+    if (rc) return rc;
+    ctmi_plan* p = new (std::nothrow) ctmi_plan();
+    if (!p) return fail(CTMI_EINVAL, "out of host memory");
+    p->geo = *geo;
+    p->nviews = nviews;
+    p->vol.nz = (int)geo->nVoxel[0];
+    p->vol.ny = (int)geo->nVoxel[1];
+    p->vol.nx = (int)geo->nVoxel[2];
+    p->vol.hz = (float)geo->dVoxel[0];
+    p->vol.hy = (float)geo->dVoxel[1];
+    p->vol.hx = (float)geo->dVoxel[2];
+    p->det.nv = (int)geo->nDetector[0];
+    p->det.nu = (int)geo->nDetector[1];
+    p->ds = (float)(geo->accuracy * std::fmin(geo->dVoxel[0], std::fmin(geo->dVoxel[1], geo->dVoxel[2])));
+    int L = 1, logL = 0;
+    while (L < 2 * p->det.nu - 1 || L < 2) {
+        L <<= 1;
+        ++logL;
+    }
+    p->fft_len = L;
+    p->fft_log2 = logL;
+
+    std::vector<ViewGeo> t(nviews);
+    view_table(geo, angles, nviews, t.data());
+    std::vector<float> Hbr, tw;
+    ramp_tables(geo, L, logL, Hbr, tw);
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    const size_t tb = sizeof(ViewGeo) * (size_t)nviews;
+    const size_t hb = sizeof(float) * (size_t)L;
+    const size_t wb = sizeof(float) * (size_t)L;  // L/2 float2
+    char* mem = nullptr;
+    e = hipMalloc(reinterpret_cast<void**>(&mem), tb + hb + wb);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMalloc(plan tables)");
+    }
+    p->d_views = reinterpret_cast<ViewGeo*>(mem);
+    p->d_filter = reinterpret_cast<float*>(mem + tb);
+    p->d_twiddle = reinterpret_cast<float2*>(mem + tb + hb);
+    if ((e = hipMemcpy(p->d_views, t.data(), tb, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_filter, Hbr.data(), hb, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_twiddle, tw.data(), wb, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(mem);
+        delete p;
+        return hip_fail(e, "hipMemcpy(plan tables)");
+    }
+    *out = p;
+    return CTMI_OK;
+}
+
+int ctmi_plan_destroy(ctmi_plan* plan)
+{
+    if (!plan) return CTMI_OK;
+    int rc = CTMI_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+    e = hipFree(plan->d_views);
+    if (e != hipSuccess && rc == CTMI_OK) rc = hip_fail(e, "hipFree");
+    delete plan;
+    return rc;
+}
+
+int ctmi_forward(const ctmi_plan* plan, int projector, const float* vol, float* proj, int64_t view0, int64_t nviews,
+                 void* stream)
+{
+    int rc;
+    if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
+    if (projector != CTMI_SIDDON && projector != CTMI_INTERP)
+        return fail(CTMI_EINVAL, "unknown projector %d", projector);
+    if (nviews == 0) return CTMI_OK;
+    if ((rc = check_ptr(vol, "vol")) || (rc = check_ptr(proj, "proj")) || (rc = check_device(plan))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return projector == CTMI_SIDDON
+               ? launched(ctmi::launch_forward_siddon(*plan, vol, proj, view0, nviews, s), "forward (Siddon)")
+               : launched(ctmi::launch_forward_interp(*plan, vol, proj, view0, nviews, s), "forward (interpolated)");
+}
+
+int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
+                     float beta, void* stream)
+{
+    int rc;
+    if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
+    if (bp != CTMI_BP_SIDDON && bp != CTMI_BP_INTERP && bp != CTMI_BP_FDK)
+        return fail(CTMI_EINVAL, "unknown backprojector %d", bp);
+    if (!std::isfinite(beta)) return fail(CTMI_EINVAL, "beta is not finite");
+    if ((rc = check_ptr(vol, "vol")) || (nviews > 0 && (rc = check_ptr(proj, "proj"))) ||
+        (rc = check_device(plan)))
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // nviews == 0 still applies vol = beta * vol (proj is not read)
+    switch (bp) {
+    case CTMI_BP_SIDDON:
+        return launched(ctmi::launch_backward_siddon(*plan, proj, vol, view0, nviews, beta, s), "backproject (Siddon)");
+    case CTMI_BP_INTERP:
+        return launched(ctmi::launch_backward_interp(*plan, proj, vol, view0, nviews, beta, s),
+                        "backproject (interpolated)");
+    default:
+        return launched(ctmi::launch_backward_fdk(*plan, proj, vol, view0, nviews, beta, s), "backproject (FDK)");
+    }
+}
+
+int ctmi_fdk_filter(const ctmi_plan* plan, int wang, const float* proj, float* out, int64_t view0, int64_t nviews,
+                    void* stream)
+{
+    int rc;
+    if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
+    if (nviews == 0) return CTMI_OK;
+    if ((rc = check_ptr(proj, "proj")) || (rc = check_ptr(out, "out")) || (rc = check_device(plan))) return rc;
+    if (wang && plan->geo.offDetector[1] != 0.0 &&
+        !(0.5 * (double)plan->det.nu * plan->geo.dDetector[1] > std::fabs(plan->geo.offDetector[1])))
+        return fail(CTMI_EINVAL, "Wang weighting needs an overlap: |offDetector_u| must be < nu du / 2");
+    return launched(ctmi::launch_fdk_filter(*plan, wang, proj, out, view0, nviews, static_cast<hipStream_t>(stream)),
+                    "FDK filter");
+}
+
+size_t ctmi_reduce_workspace_bytes(int64_t n)
+{
+    (void)n;
+    return ctmi::reduce_ws_bytes();
+}
+
+static int check_ws(const void* ws, size_t ws_bytes)
+{
+    if (!ws) return fail(CTMI_EWORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 8 != 0) return fail(CTMI_EINVAL, "workspace is not 8-byte aligned");
+    if (ws_bytes < ctmi::reduce_ws_bytes())
+        return fail(CTMI_EWORKSPACE, "workspace of %zu bytes is below the %zu required", ws_bytes,
+                    ctmi::reduce_ws_bytes());
+    return CTMI_OK;
+}
+
+static int check_n(int64_t n)
+{
+    if (n < 0) return fail(CTMI_EINVAL, "negative length");
+    return CTMI_OK;
+}
+
+int ctmi_dot(const float* a, const float* b, int64_t n, double* out, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(a, "a")) || (rc = check_ptr(b, "b")) || (rc = check_ws(ws, ws_bytes)))
+        return rc;
+    if (!out || reinterpret_cast<uintptr_t>(out) % 8) return fail(CTMI_EINVAL, "out must be an aligned double");
+    return launched(ctmi::launch_dot(a, b, n, out, static_cast<double*>(ws), static_cast<hipStream_t>(stream)), "dot");
+}
+
+int ctmi_axpby(int64_t n, float a, const float* x, float b, float* y, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n))) return rc;
+    if (n == 0) return CTMI_OK;
+    if ((rc = check_ptr(x, "x")) || (rc = check_ptr(y, "y"))) return rc;
+    return launched(ctmi::launch_axpby(n, a, x, b, y, static_cast<hipStream_t>(stream)), "axpby");
+}
+
+int ctmi_cgls_xr(float* x, const float* p, int64_t nvol, float* r, const float* q, int64_t nproj, const double* gamma,
+                 const double* delta, double* rnorm2, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc;
+    if ((rc = check_n(nvol)) || (rc = check_n(nproj)) || (rc = check_ptr(x, "x")) || (rc = check_ptr(p, "p")) ||
+        (rc = check_ptr(r, "r")) || (rc = check_ptr(q, "q")) || (rc = check_ws(ws, ws_bytes)))
+        return rc;
+    if (!gamma || !delta || !rnorm2) return fail(CTMI_EINVAL, "gamma, delta and rnorm2 must be device doubles");
+    return launched(ctmi::launch_cgls_xr(x, p, nvol, r, q, nproj, gamma, delta, rnorm2, static_cast<double*>(ws),
+                                         static_cast<hipStream_t>(stream)),
+                    "cgls_xr");
+}
+
+int ctmi_cgls_p(float* p, const float* s, int64_t n, const double* gamma_old, const double* gamma_new, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(p, "p")) || (rc = check_ptr(s, "s"))) return rc;
+    if (!gamma_old || !gamma_new) return fail(CTMI_EINVAL, "gamma_old and gamma_new must be device doubles");
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_cgls_p(p, s, n, gamma_old, gamma_new, static_cast<hipStream_t>(stream)), "cgls_p");
+}
+
+int ctmi_recip_or_zero(const float* in, float* out, int64_t n, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(in, "in")) || (rc = check_ptr(out, "out"))) return rc;
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_recip(in, out, n, static_cast<hipStream_t>(stream)), "recip_or_zero");
+}
+
+int ctmi_sart_residual(const float* b, const float* ax, const float* w, float* out, int64_t n, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(b, "b")) || (rc = check_ptr(ax, "ax")) || (rc = check_ptr(w, "w")) ||
+        (rc = check_ptr(out, "out")))
+        return rc;
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_sart_residual(b, ax, w, out, n, static_cast<hipStream_t>(stream)), "sart_residual");
+}
+
+int ctmi_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(x, "x")) || (rc = check_ptr(v, "v")) || (rc = check_ptr(bp, "bp")))
+        return rc;
+    if (!std::isfinite(lam)) return fail(CTMI_EINVAL, "lam is not finite");
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_sart_update(x, v, bp, n, lam, nonneg, static_cast<hipStream_t>(stream)),
+                    "sart_update");
+}
+
+int ctmi_fov_sq_err(const ctmi_plan* plan, const float* x, const float* gt, double* out, void* ws, size_t ws_bytes,
+                    void* stream)
+{
+    int rc;
+    if ((rc = check_plan(plan)) || (rc = check_ptr(x, "x")) || (rc = check_ptr(gt, "gt")) ||
+        (rc = check_ws(ws, ws_bytes)) || (rc = check_device(plan)))
+        return rc;
+    if (!out) return fail(CTMI_EINVAL, "out is NULL");
+    return launched(ctmi::launch_fov_sq_err(*plan, x, gt, out, static_cast<double*>(ws), static_cast<hipStream_t>(stream)),
+                    "fov_sq_err");
+}
+
+}  // extern "C"

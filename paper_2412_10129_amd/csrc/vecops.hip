@@ -1,0 +1,236 @@
+// Vector kernels of the iterative methods: CGLS (section 2.2.1), OS-SART
+// (section 2.2.2) and the error history (section 2.2.3).  All are streaming
+// HBM-bound loops; reductions accumulate in FP64 with a fixed blocking and
+// a fixed tree order, so results are bit-reproducible for a given n.
+#include "ctmi_internal.h"
+
+namespace ctmi {
+
+namespace {
+
+constexpr int RB = 256;          // threads per reduction block
+constexpr int RMAX = 1024;       // max partial sums
+
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ void __launch_bounds__(RB) k_final_sum(const double* __restrict__ part, int nparts, int nvals,
+                                                  double* out)
+{
+    __shared__ double sh[RB];
+    for (int c = 0; c < nvals; ++c) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nparts; i += RB) s += part[c * RMAX + i];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) out[c] = s;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_dot_partial(const float* __restrict__ a, const float* __restrict__ b,
+                                                    int64_t n, double* __restrict__ part)
+{
+    __shared__ double sh[RB];
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RB;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride)
+        s += (double)a[i] * (double)b[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_axpby(int64_t n, float a, const float* __restrict__ x, float b,
+                                               float* __restrict__ y)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        y[i] = __builtin_fmaf(a, x[i], b * y[i]);
+}
+
+__device__ __forceinline__ float safe_ratio(const double* num, const double* den)
+{
+    const double d = *den;
+    return d != 0.0 ? (float)(*num / d) : 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_cgls_x(float* __restrict__ x, const float* __restrict__ p, int64_t n,
+                                                const double* gamma, const double* delta)
+{
+    const float alpha = safe_ratio(gamma, delta);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        x[i] = __builtin_fmaf(alpha, p[i], x[i]);
+}
+
+__global__ void __launch_bounds__(RB) k_cgls_r(float* __restrict__ r, const float* __restrict__ q, int64_t n,
+                                               const double* gamma, const double* delta, double* __restrict__ part)
+{
+    __shared__ double sh[RB];
+    const float alpha = safe_ratio(gamma, delta);
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RB;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
+        const float v = __builtin_fmaf(-alpha, q[i], r[i]);
+        r[i] = v;
+        s += (double)v * (double)v;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_cgls_p(float* __restrict__ p, const float* __restrict__ s_, int64_t n,
+                                                const double* g0, const double* g1)
+{
+    const float beta = safe_ratio(g1, g0);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = __builtin_fmaf(beta, p[i], s_[i]);
+}
+
+__global__ void __launch_bounds__(256) k_recip(const float* in, float* out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float v = in[i];
+        out[i] = v != 0.0f ? 1.0f / v : 0.0f;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sart_residual(const float* __restrict__ b, const float* ax,
+                                                       const float* __restrict__ w, float* out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = w[i] * (b[i] - ax[i]);
+}
+
+__global__ void __launch_bounds__(256) k_sart_update(float* __restrict__ x, const float* __restrict__ v,
+                                                     const float* __restrict__ bp, int64_t n, float lam, int nonneg)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float y = __builtin_fmaf(lam * v[i], bp[i], x[i]);
+        if (nonneg) y = fmaxf(y, 0.0f);
+        x[i] = y;
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_fov_partial(const float* __restrict__ x, const float* __restrict__ gt,
+                                                    VolDims v, float cx, float cy, float r2,
+                                                    double* __restrict__ part)
+{
+    __shared__ double sh[RB];
+    const int64_t n = (int64_t)v.nx * v.ny * v.nz;
+    double s = 0.0, c = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * RB;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
+        const int ix = (int)(i % v.nx);
+        const int iy = (int)((i / v.nx) % v.ny);
+        const float X = ((float)ix - cx) * v.hx, Y = ((float)iy - cy) * v.hy;
+        if (__builtin_fmaf(X, X, Y * Y) <= r2) {
+            const double d = (double)x[i] - (double)gt[i];
+            s += d * d;
+            c += 1.0;
+        }
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    __syncthreads();
+    c = block_sum(c, sh);
+    if (threadIdx.x == 0) part[RMAX + blockIdx.x] = c;
+}
+
+unsigned stream_blocks(int64_t n)
+{
+    int64_t b = (n + 256 * 8 - 1) / (256 * 8);
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+int reduce_blocks(int64_t n)
+{
+    int64_t b = (n + RB * 16 - 1) / (RB * 16);
+    if (b < 1) b = 1;
+    if (b > RMAX) b = RMAX;
+    return (int)b;
+}
+
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* out, double* ws, hipStream_t s)
+{
+    const int g = reduce_blocks(n);
+    hipLaunchKernelGGL(k_dot_partial, dim3(g), dim3(RB), 0, s, a, b, n, ws);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(RB), 0, s, ws, g, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, float a, const float* x, float b, float* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(stream_blocks(n)), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgls_xr(float* x, const float* p, int64_t nvol, float* r, const float* q, int64_t nproj,
+                          const double* gamma, const double* delta, double* rnorm2, double* ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cgls_x, dim3(stream_blocks(nvol)), dim3(256), 0, s, x, p, nvol, gamma, delta);
+    const int g = reduce_blocks(nproj);
+    hipLaunchKernelGGL(k_cgls_r, dim3(g), dim3(RB), 0, s, r, q, nproj, gamma, delta, ws);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(RB), 0, s, ws, g, 1, rnorm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cgls_p(float* p, const float* s_, int64_t n, const double* g0, const double* g1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cgls_p, dim3(stream_blocks(n)), dim3(256), 0, s, p, s_, n, g0, g1);
+    return hipGetLastError();
+}
+
+hipError_t launch_recip(const float* in, float* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_recip, dim3(stream_blocks(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sart_residual(const float* b, const float* ax, const float* w, float* out, int64_t n,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sart_residual, dim3(stream_blocks(n)), dim3(256), 0, s, b, ax, w, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sart_update, dim3(stream_blocks(n)), dim3(256), 0, s, x, v, bp, n, lam, nonneg);
+    return hipGetLastError();
+}
+
+hipError_t launch_fov_sq_err(const Plan& p, const float* x, const float* gt, double* out, double* ws,
+                             hipStream_t s)
+{
+    const int64_t n = (int64_t)p.vol.nx * p.vol.ny * p.vol.nz;
+    const int g = reduce_blocks(n);
+    // voxel-centre index of the volume centre; the cylinder is centred on the
+    // volume (its offset does not change the index geometry)
+    const float cx = 0.5f * (float)p.vol.nx - 0.5f, cy = 0.5f * (float)p.vol.ny - 0.5f;
+    const double R = 0.5 * ((double)p.vol.ny * p.vol.hy < (double)p.vol.nx * p.vol.hx ? (double)p.vol.ny * p.vol.hy
+                                                                                       : (double)p.vol.nx * p.vol.hx);
+    hipLaunchKernelGGL(k_fov_partial, dim3(g), dim3(RB), 0, s, x, gt, p.vol, cx, cy, (float)(R * R), ws);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(RB), 0, s, ws, g, 2, out);
+    return hipGetLastError();
+}
+
+size_t reduce_ws_bytes() { return sizeof(double) * 2 * RMAX; }
+
+}  // namespace ctmi

@@ -1,0 +1,217 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (rel-L2 unless stated): A and A^T 1e-4; FDK 1e-4; CGLS after
+20 iterations 1e-3; GPU dot-product identity 1e-5.  Sizes are chosen so the
+oracle finishes in seconds while spanning several 16x16 ray tiles and 16^3
+bricks with ragged tails.
+"""
+import numpy as np
+import pytest
+
+import synth
+from synth import Geometry
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# ragged sizes: 44 x 36 x 40 voxels (bricks of 16 leave tails), detector
+# 50 x 70 (tiles of 16 leave tails), anisotropic voxels, all offsets nonzero
+RAGGED = Geometry(DSD=400.0, DSO=250.0, nVoxel=(40, 36, 44), dVoxel=(1.1, 1.0, 0.9), nDetector=(50, 70),
+                  dDetector=(1.3, 1.2), offOrigin=(0.7, -1.1, 0.4), offDetector=(0.9, -1.6))
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_10129_amd as P
+    return P
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _angles(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.uniform(0, 2 * np.pi, n))
+
+
+CASES = {
+    "ragged": lambda: (RAGGED, _angles(24, 1)),
+    "head64": lambda: synth.workload("head64"),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_forward_matches_oracle(P, orc, case, kind):
+    geo, ang = CASES[case]()
+    if case == "head64":
+        x = synth.voxelize(geo, synth.head_phantom(geo, 1))
+    else:
+        x = synth.uniform_volume(geo, 2)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.forward(_dev(x), kind=kind))
+    want = orc.forward(geo, ang, x, kind)
+    assert _rel(got, want) < 1e-4, (case, kind, _rel(got, want))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_backward_matches_oracle(P, orc, case, kind):
+    geo, ang = CASES[case]()
+    y = synth.uniform_projections(geo, len(ang), 3)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.backproject(_dev(y), kind=kind))
+    want = orc.backward(geo, ang, y, kind)
+    assert _rel(got, want) < 1e-4, (case, kind, _rel(got, want))
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_gpu_dot_product_identity(P, kind):
+    geo, ang = RAGGED, _angles(24, 4)
+    plan = P.Plan(geo, ang)
+    x = _dev(synth.uniform_volume(geo, 5))
+    y = _dev(synth.uniform_projections(geo, len(ang), 6))
+    ax = plan.forward(x, kind=kind)
+    aty = plan.backproject(y, kind=kind)
+    lhs = float(_host(P.dot(ax, y))[0])
+    rhs = float(_host(P.dot(x, aty))[0])
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp", "fdk"])
+def test_view_ranges_and_beta_accumulation(P, kind):
+    """A on a view range equals the slice of A on all views; backprojecting
+    two view ranges with beta = 1 equals one call over both."""
+    geo, ang = RAGGED, _angles(20, 7)
+    plan = P.Plan(geo, ang)
+    x = _dev(synth.uniform_volume(geo, 8))
+    y = _dev(synth.uniform_projections(geo, len(ang), 9))
+    if kind != "fdk":
+        full = _host(plan.forward(x, kind=kind))
+        part = _host(plan.forward(x, kind=kind, view0=7, nviews=9))
+        assert np.array_equal(part, full[7:16])
+    whole = _host(plan.backproject(y, kind=kind))
+    acc = plan.backproject(y[:12].contiguous(), kind=kind, view0=0, nviews=12)
+    plan.backproject(y[12:].contiguous(), out=acc, kind=kind, beta=1.0, view0=12, nviews=8)
+    assert _rel(_host(acc), whole) < 1e-6
+    # beta scales the old contents
+    base = torch.full(plan.vol_shape, 2.0, device="cuda")
+    plan.backproject(y, out=base, kind=kind, beta=0.5)
+    assert _rel(_host(base), whole + 1.0) < 1e-6
+
+
+def test_fdk_filter_matches_oracle(P, orc):
+    geo, ang = synth.workload("head64")
+    y = synth.uniform_projections(geo, len(ang), 10)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.fdk_filter(_dev(y)))
+    want = orc.fdk_filter(geo, y, len(ang))
+    assert _rel(got, want) < 1e-5
+
+
+def test_fdk_filter_wang_and_odd_rows(P, orc):
+    """Offset detector with Wang weights; an odd number of rows exercises
+    the unpaired last row of the two-rows-per-FFT packing; in-place."""
+    geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(8, 64, 64), dVoxel=(1.0, 1.0, 1.0), nDetector=(15, 56),
+                   dDetector=(1.6, 1.6), offDetector=(0.3, 12.0))
+    ang = synth.circular_angles(9)
+    y = synth.uniform_projections(geo, len(ang), 11)
+    plan = P.Plan(geo, ang)
+    t = _dev(y)
+    plan.fdk_filter(t, out=t, wang=True)
+    want = orc.fdk_filter(geo, y, len(ang), wang=True)
+    assert _rel(_host(t), want) < 1e-5
+
+
+def test_bfdk_matches_oracle(P, orc):
+    geo, ang = RAGGED, _angles(24, 12)
+    y = synth.uniform_projections(geo, len(ang), 13)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.backproject(_dev(y), kind="fdk"))
+    want = orc.bfdk(geo, ang, y)
+    assert _rel(got, want) < 1e-5
+
+
+def test_fdk_head64_end_to_end(P, orc):
+    geo, ang = synth.workload("head64")
+    x = synth.voxelize(geo, synth.head_phantom(geo, 1))
+    b = orc.forward(geo, ang, x, "siddon")
+    plan = P.Plan(geo, ang)
+    got = _host(P.fdk(plan, _dev(b)))
+    want = orc.fdk(geo, ang, b)
+    assert _rel(got, want) < 1e-4
+
+
+def test_edge_cases(P, orc):
+    """One-pixel detector, one view, single-slice volume, an empty view range."""
+    geo = Geometry(DSD=300.0, DSO=200.0, nVoxel=(1, 9, 7), dVoxel=(1.0, 1.0, 1.0), nDetector=(1, 1),
+                   dDetector=(1.0, 1.0), offDetector=(0.2, 0.3))
+    ang = np.array([0.4])
+    x = synth.uniform_volume(geo, 14)
+    plan = P.Plan(geo, ang)
+    for kind in ("siddon", "interp"):
+        got = _host(plan.forward(_dev(x), kind=kind))
+        assert _rel(got, orc.forward(geo, ang, x, kind)) < 1e-5
+        y = np.array([[[1.7]]], dtype=np.float32)
+        assert _rel(_host(plan.backproject(_dev(y), kind=kind)), orc.backward(geo, ang, y, kind)) < 1e-5
+    out = torch.full((0,) + plan.det_shape, 3.0, device="cuda")
+    plan.forward(_dev(x), out=out, nviews=0)
+    v = torch.ones(plan.vol_shape, device="cuda")
+    plan.backproject(torch.zeros((0,) + plan.det_shape, device="cuda") + 1, out=v, beta=2.0, view0=1, nviews=0)
+    assert np.all(_host(v) == 2.0)
+
+
+def test_forward_is_bit_reproducible(P):
+    geo, ang = RAGGED, _angles(12, 15)
+    plan = P.Plan(geo, ang)
+    x = _dev(synth.uniform_volume(geo, 16))
+    for kind in ("siddon", "interp"):
+        a = _host(plan.forward(x, kind=kind))
+        b = _host(plan.forward(x, kind=kind))
+        assert np.array_equal(a, b)
+
+
+def test_cgls_matches_oracle(P, orc):
+    geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(48, 64, 64), dVoxel=(1.0, 1.0, 1.0), nDetector=(64, 96),
+                   dDetector=(1.6, 1.6))
+    ang = synth.circular_angles(48)
+    ell = synth.random_ellipsoids(geo, 2)
+    x_gt = synth.voxelize(geo, ell)
+    b = synth.poisson_log_data(orc.forward(geo, ang, x_gt, "interp"), seed=3).astype(np.float32)
+    plan = P.Plan(geo, ang)
+    xg, hg = P.cgls(plan, _dev(b), 20, kind="interp", x_gt=_dev(x_gt))
+    xo, ho = orc.cgls(geo, ang, b, 20, kind="interp", x_gt=x_gt, mask=orc.fov_mask(geo))
+    assert _rel(_host(xg), xo) < 1e-3, _rel(_host(xg), xo)
+    assert _rel(hg["resid"], ho["resid"]) < 1e-3
+    R = float(x_gt[orc.fov_mask(geo)].max() - x_gt[orc.fov_mask(geo)].min())
+    psnr = P.psnr_from_sq_err(hg["sq_err"], hg["count"], R)
+    assert np.allclose(psnr, ho["psnr"], atol=0.01)
+
+
+@pytest.mark.parametrize("blocksize,nonneg", [(8, True), (1, False), (24, True)])
+def test_os_sart_matches_oracle(P, orc, blocksize, nonneg):
+    geo = Geometry(DSD=400.0, DSO=250.0, nVoxel=(20, 24, 28), dVoxel=(1.0, 1.0, 1.0), nDetector=(30, 40),
+                   dDetector=(1.3, 1.3))
+    ang = synth.circular_angles(24)
+    x_gt = synth.uniform_volume(geo, 17)
+    b = orc.forward(geo, ang, x_gt, "interp") + 0.05 * np.random.Generator(np.random.PCG64(18)).standard_normal(
+        (24,) + geo.nDetector)
+    plan = P.Plan(geo, ang)
+    got = _host(P.os_sart(plan, _dev(b), 2, blocksize, lam=0.9, nonneg=nonneg, kind="interp"))
+    want = orc.os_sart(geo, ang, b.astype(np.float32), 2, blocksize, lam=0.9, nonneg=nonneg, kind="interp")
+    assert _rel(got, want) < 1e-4, _rel(got, want)
