@@ -53,10 +53,10 @@ __device__ __forceinline__ bool footprint(const ViewGeo& g, const float lo[3], c
         vmax = fmaxf(vmax, V * rw);
     }
     // clamp in float first: the corners may project far outside the detector
-    umin = fmaxf(umin, -2.0f);
-    vmin = fmaxf(vmin, -2.0f);
-    umax = fminf(umax, (float)det.nu + 1.0f);
-    vmax = fminf(vmax, (float)det.nv + 1.0f);
+    umin = fminf(fmaxf(umin, -2.0f), (float)det.nu + 1.0f);
+    vmin = fminf(fmaxf(vmin, -2.0f), (float)det.nv + 1.0f);
+    umax = fminf(fmaxf(umax, -2.0f), (float)det.nu + 1.0f);
+    vmax = fminf(fmaxf(vmax, -2.0f), (float)det.nv + 1.0f);
     u0 = max((int)__builtin_floorf(umin) - 1, 0);
     v0 = max((int)__builtin_floorf(vmin) - 1, 0);
     u1 = min((int)__builtin_ceilf(umax) + 1, det.nu - 1);
