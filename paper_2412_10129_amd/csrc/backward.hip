@@ -2,22 +2,45 @@
 // interpolated forward projectors (needed by the Krylov methods of section
 // 2.2.1, and as the gradient of the autograd operator).
 //
-// Voxel-driven by bricks: a workgroup owns one BxBxB brick of output voxels
-// and accumulates it in LDS over every view of the call; each voxel has one
-// writer in global memory and no global atomics are used.  Per view, the
-// brick's detector footprint (the bounding box of its projected corners) is
-// enumerated; each footprint ray is re-traced inside the brick only, with the
-// same FP32 arithmetic as the forward kernel (shared helpers in
-// ctmi_internal.h), and its in-brick matrix entries a_ij * y_i are added to
-// the LDS accumulators.  Bricks are ordered z-slab-major so the workgroups in
-// flight read the same detector row band of every view.
+// Voxel-driven by bricks: a workgroup owns one 16x16x8 brick of output voxels
+// and accumulates it over every view of the call; each voxel has one writer
+// in global memory and no global atomics are used.  Per view, the brick's
+// detector footprint (bounding box of its projected corners) is enumerated
+// in rounds of 256 pixels: each thread re-traces one pixel's ray inside the
+// brick, with the same FP32 arithmetic as the forward kernel (shared helpers
+// in ctmi_internal.h), and records it in an LDS ray table; the rays' work is
+// cut into items of bounded size (a few cells or samples), numbered by a
+// block scan, and processed round-robin so rays of different lengths keep
+// every lane busy.
+//
+// Accumulation is in 64-bit fixed point in LDS: FP32 LDS atomics are
+// serialised on gfx950 (about 0.3 lane-ops per CU clock) while 64-bit
+// integer LDS atomics run about 30x faster.  Per (brick, view) the scale is
+// the largest power of two that keeps the view's total contribution to any
+// voxel below 2^60, from the footprint's max |y| and a geometric bound on
+// sum_i |a_ij| per view, so every FP32 contribution keeps its full precision;
+// after each view the integers are converted (exact power-of-two scaling)
+// into per-thread FP32 registers in view order.  Integer addition is
+// associative, so the result is bit-reproducible.
 #include "ctmi_internal.h"
 
 namespace ctmi {
 
 namespace {
 
-constexpr int BRICK = 16;
+#ifndef CTMI_BWD_BZ
+#define CTMI_BWD_BZ 8
+#endif
+#ifndef CTMI_BWD_SID_CELLS
+#define CTMI_BWD_SID_CELLS 4
+#endif
+#ifndef CTMI_BWD_INT_SAMPLES
+#define CTMI_BWD_INT_SAMPLES 8
+#endif
+constexpr int BX = 16, BY = 16, BZ = CTMI_BWD_BZ;   // brick (voxels)
+constexpr int NB = BX * BY * BZ;
+constexpr int OWN = NB / 256;                     // voxels owned per thread
+typedef unsigned long long u64;
 
 struct BrickMap {
     int nbx, nby, nbz;
@@ -64,175 +87,395 @@ __device__ __forceinline__ bool footprint(const ViewGeo& g, const float lo[3], c
     return u0 <= u1 && v0 <= v1;
 }
 
-__device__ __forceinline__ void store_brick(float* __restrict__ vol, const float* acc, const VolDims& v, int x0,
+// Exclusive prefix sum of one int per thread over a 256-thread block; returns
+// this thread's offset and the block total.  `wsum` holds 4 ints of LDS.
+__device__ __forceinline__ int block_scan(int v, int* wsum, int* total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = wsum[i];
+        off += i < w ? t : 0;
+        tot += t;
+    }
+    *total = tot;
+    return off + x - v;
+}
+
+// Largest r in [0, 255] with pre[r] <= it (pre non-decreasing).
+__device__ __forceinline__ int owner(const int* pre, int it)
+{
+    int lo = 0, hi = 255;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Fixed-point scale for one (brick, view): the largest power of two s with
+// s * bound * maxy <= 2^60.  Returns s and writes 1/s.
+__device__ __forceinline__ float fixed_scale(float bound, float maxy, float* inv)
+{
+    int e;
+    (void)__builtin_frexpf(0x1p60f / (bound * maxy), &e);
+    e = min(max(e - 1, -120), 120);
+    *inv = __builtin_ldexpf(1.0f, -e);
+    return __builtin_ldexpf(1.0f, e);
+}
+
+// Two's-complement 64-bit fixed-point value of q (|q| < 2^62): the high word
+// is floor(q / 2^32) and the low word the remainder in [0, 2^32), rounded to
+// FP32 (an error of at most 256 units of 2^-60 of the scale) and clamped
+// below 2^32 so the unsigned conversion is always in range.
+__device__ __forceinline__ u64 to_fixed(float q)
+{
+    const float hi = __builtin_floorf(q * 0x1p-32f);
+    const float lo = fminf(fmaxf(__builtin_fmaf(-hi, 0x1p32f, q), 0.0f), 4294967040.0f);
+    return ((u64)(unsigned)(int)hi << 32) | (u64)(unsigned)lo;
+}
+
+// Max |y| over the footprint pixels [u0, u1] x [v0, v1] of view image pk,
+// reduced over the block (LDS word `red`, as the bits of a non-negative float).
+__device__ __forceinline__ float footprint_max(const float* __restrict__ pk, const DetDims& det, int u0, int u1,
+                                               int v0, int v1, unsigned* red)
+{
+    const int w = u1 - u0 + 1, npx = w * (v1 - v0 + 1);
+    float m = 0.0f;
+    for (int p = threadIdx.x; p < npx; p += blockDim.x) {
+        const int r = p / w;
+        m = fmaxf(m, fabsf(pk[(int64_t)(v0 + r) * det.nu + u0 + (p - r * w)]));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(red, __float_as_uint(m));
+    __syncthreads();
+    return __uint_as_float(*red);
+}
+
+// Add the view's fixed-point sums into the owned FP32 registers and clear
+// the integer accumulator (voxel (lx, ly, lz) of the brick sits at
+// ((lz + pad) * py + ly + pad) * px + lx + pad).
+__device__ __forceinline__ void flush_view(u64* acc, int n_acc, int px, int py, int pad, float inv, float own[OWN])
+{
+#pragma unroll
+    for (int m = 0; m < OWN; ++m) {
+        const int i = threadIdx.x + 256 * m;
+        const int lx = i % BX, ly = (i / BX) % BY, lz = i / (BX * BY);
+        const long long a = (long long)acc[((lz + pad) * py + (ly + pad)) * px + (lx + pad)];
+        own[m] = __builtin_fmaf((float)a, inv, own[m]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0ull;
+}
+
+__device__ __forceinline__ void store_owned(float* __restrict__ vol, const float own[OWN], const VolDims& v, int x0,
                                             int y0, int z0, float beta)
 {
-    for (int i = threadIdx.x; i < BRICK * BRICK * BRICK; i += blockDim.x) {
-        const int lx = i % BRICK, ly = (i / BRICK) % BRICK, lz = i / (BRICK * BRICK);
-        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+#pragma unroll
+    for (int m = 0; m < OWN; ++m) {
+        const int i = threadIdx.x + 256 * m;
+        const int gx = x0 + i % BX, gy = y0 + (i / BX) % BY, gz = z0 + i / (BX * BY);
         if (gx >= v.nx || gy >= v.ny || gz >= v.nz) continue;
         float* o = vol + ((int64_t)gz * v.ny + gy) * v.nx + gx;
-        *o = beta == 0.0f ? acc[i] : __builtin_fmaf(beta, *o, acc[i]);
+        *o = beta == 0.0f ? own[m] : __builtin_fmaf(beta, *o, own[m]);
     }
 }
 
+constexpr int SID_CELLS = CTMI_BWD_SID_CELLS;   // dominant-axis cells per Siddon item
+
 __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab, int view0, int nviews,
-                                                         VolDims v, DetDims det, BrickMap m, float beta)
+                                                         VolDims v, DetDims det, BrickMap m, float beta, float bound)
 {
-    __shared__ float acc[BRICK * BRICK * BRICK];
-    for (int i = threadIdx.x; i < BRICK * BRICK * BRICK; i += blockDim.x) acc[i] = 0.0f;
+    __shared__ u64 acc[NB];
+    __shared__ float t_S[3][256], t_d[3][256];
+    __shared__ float t_a0[256], t_a1[256], t_y[256];
+    __shared__ int t_c0[256], t_nc[256], t_pre[256];
+    __shared__ int wsum[4];
+    __shared__ unsigned red;
+    for (int i = threadIdx.x; i < NB; i += blockDim.x) acc[i] = 0ull;
+    float own[OWN];
+#pragma unroll
+    for (int i = 0; i < OWN; ++i) own[i] = 0.0f;
     int bx, by, bz;
     brick_origin(m, blockIdx.x, bx, by, bz);
-    const int x0 = bx * BRICK, y0 = by * BRICK, z0 = bz * BRICK;
-    const int x1 = min(x0 + BRICK, v.nx), y1 = min(y0 + BRICK, v.ny), z1 = min(z0 + BRICK, v.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
+    const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
+    const int b0[3] = {x0, y0, z0}, b1[3] = {x1, y1, z1};
     const float lo[3] = {x0 - 0.5f, y0 - 0.5f, z0 - 0.5f};   // cell box in voxel-centre coordinates
     const float hi[3] = {x1 - 0.5f, y1 - 0.5f, z1 - 0.5f};
-    __syncthreads();
+    const int tid = threadIdx.x;
 
     for (int k = 0; k < nviews; ++k) {
         const ViewGeo& g = tab[view0 + k];
         int u0, u1, vv0, vv1;
         if (!footprint(g, lo, hi, det, u0, u1, vv0, vv1)) continue;
+        const float* pk = proj + (int64_t)k * det.nv * det.nu;
+        if (tid == 0) red = 0u;
+        __syncthreads();
+        const float maxy = footprint_max(pk, det, u0, u1, vv0, vv1, &red);
+        if (!(maxy > 0.0f)) continue;
+        float inv;
+        const float scale = fixed_scale(bound, maxy, &inv);
         const int w = u1 - u0 + 1;
         const int npx = w * (vv1 - vv0 + 1);
-        const float* pk = proj + (int64_t)k * det.nv * det.nu;
-        for (int p = threadIdx.x; p < npx; p += blockDim.x) {
-            const int r = p / w;
-            const int iv = vv0 + r, iu = u0 + (p - r * w);
-            float S[3], d[3];
-            pixel_ray(g, iu, iv, S, d);
-            const SiddonAxis ax = siddon_axis(S[0], d[0]);
-            const SiddonAxis ay = siddon_axis(S[1], d[1]);
-            const SiddonAxis az = siddon_axis(S[2], d[2]);
-            float amin = 0.0f, amax = 1.0f;
-            bool hit = slab_clip(ax, S[0], (float)x0, (float)x1, amin, amax);
-            hit &= slab_clip(ay, S[1], (float)y0, (float)y1, amin, amax);
-            hit &= slab_clip(az, S[2], (float)z0, (float)z1, amin, amax);
-            if (!hit || !(amin < amax)) continue;
-            const float yl = pk[(int64_t)iv * det.nu + iu] * world_length(d, v);
-            int ix = entry_cell(S[0], d[0], amin, ax.step, x0, x1);
-            int iy = entry_cell(S[1], d[1], amin, ay.step, y0, y1);
-            int iz = entry_cell(S[2], d[2], amin, az.step, z0, z1);
-            float qx = (float)(ix + (ax.step > 0)), qy = (float)(iy + (ay.step > 0)), qz = (float)(iz + (az.step > 0));
-            float anx = plane_alpha(ax, qx), any = plane_alpha(ay, qy), anz = plane_alpha(az, qz);
-            int li = ((iz - z0) * BRICK + (iy - y0)) * BRICK + (ix - x0);
-            const int sx = ax.step, sy = ay.step * BRICK, sz = az.step * BRICK * BRICK;
-            float acur = amin;
-            for (int it = 0; it < 3 * BRICK + 3; ++it) {
-                const float an = fminf(anx, fminf(any, anz));
-                const float ae = fminf(an, amax);
-                atomicAdd(&acc[li], fmaxf(ae - acur, 0.0f) * yl);
-                if (an >= amax) break;
-                acur = an;
-                if (an == anx) {
-                    ix += ax.step;
-                    if (ix < x0 || ix >= x1) break;
-                    li += sx;
-                    qx += (float)ax.step;
-                    anx = plane_alpha(ax, qx);
-                } else if (an == any) {
-                    iy += ay.step;
-                    if (iy < y0 || iy >= y1) break;
-                    li += sy;
-                    qy += (float)ay.step;
-                    any = plane_alpha(ay, qy);
-                } else {
-                    iz += az.step;
-                    if (iz < z0 || iz >= z1) break;
-                    li += sz;
-                    qz += (float)az.step;
-                    anz = plane_alpha(az, qz);
+        for (int p0 = 0; p0 < npx; p0 += 256) {
+            const int p = p0 + tid;
+            int cnt = 0;
+            if (p < npx) {
+                const int r = p / w;
+                const int iv = vv0 + r, iu = u0 + (p - r * w);
+                float S[3], d[3];
+                pixel_ray(g, iu, iv, S, d);
+                const SiddonAxis ax[3] = {siddon_axis(S[0], d[0]), siddon_axis(S[1], d[1]), siddon_axis(S[2], d[2])};
+                float amin = 0.0f, amax = 1.0f;
+                bool hit = slab_clip(ax[0], S[0], (float)x0, (float)x1, amin, amax);
+                hit &= slab_clip(ax[1], S[1], (float)y0, (float)y1, amin, amax);
+                hit &= slab_clip(ax[2], S[2], (float)z0, (float)z1, amin, amax);
+                // the ray's dominant axis (largest |d|, never parallel to its planes)
+                const int dom = (fabsf(d[0]) >= fabsf(d[1]) && fabsf(d[0]) >= fabsf(d[2])) ? 0
+                                : (fabsf(d[1]) >= fabsf(d[2]) ? 1 : 2);
+                if (hit && amin < amax) {
+                    // dominant-axis cells from entry to exit
+                    const int c0 = entry_cell(S[dom], d[dom], amin, ax[dom].step, b0[dom], b1[dom]);
+                    const int c1 = entry_cell(S[dom], -d[dom], -amax, -ax[dom].step, b0[dom], b1[dom]);
+                    const int nc = (c1 - c0) * ax[dom].step + 1;
+                    if (nc > 0) {
+                        cnt = (nc + SID_CELLS - 1) / SID_CELLS;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            t_S[a][tid] = S[a];
+                            t_d[a][tid] = d[a];
+                        }
+                        t_a0[tid] = amin;
+                        t_a1[tid] = amax;
+                        t_c0[tid] = c0 * 4 + dom;
+                        t_nc[tid] = nc;
+                        t_y[tid] = pk[(int64_t)iv * det.nu + iu] * world_length(d, v) * scale;
+                    }
                 }
             }
+            int total;
+            const int off = block_scan(cnt, wsum, &total);
+            t_pre[tid] = off;
+            __syncthreads();
+            for (int it = tid; it < total; it += 256) {
+                const int r = owner(t_pre, it);
+                const int q = it - t_pre[r];
+                const float S[3] = {t_S[0][r], t_S[1][r], t_S[2][r]};
+                const float d[3] = {t_d[0][r], t_d[1][r], t_d[2][r]};
+                const SiddonAxis ax = siddon_axis(S[0], d[0]);
+                const SiddonAxis ay = siddon_axis(S[1], d[1]);
+                const SiddonAxis az = siddon_axis(S[2], d[2]);
+                const int dom = t_c0[r] & 3, c0 = t_c0[r] >> 2;
+                const SiddonAxis& ad = dom == 0 ? ax : (dom == 1 ? ay : az);
+                const int nc = t_nc[r];
+                const int cfirst = c0 + ad.step * q * SID_CELLS;
+                const int clast = c0 + ad.step * min(q * SID_CELLS + SID_CELLS - 1, nc - 1);
+                // the item spans dominant-axis cells cfirst..clast; its ends are
+                // the planes the forward walk crosses there (same formula)
+                const float astart = q == 0 ? t_a0[r] : plane_alpha(ad, (float)(cfirst + (ad.step < 0)));
+                const float aend = (q * SID_CELLS + SID_CELLS >= nc) ? t_a1[r]
+                                                                     : plane_alpha(ad, (float)(clast + (ad.step > 0)));
+                int ix = entry_cell(S[0], d[0], astart, ax.step, x0, x1);
+                int iy = entry_cell(S[1], d[1], astart, ay.step, y0, y1);
+                int iz = entry_cell(S[2], d[2], astart, az.step, z0, z1);
+                if (dom == 0) ix = cfirst;
+                else if (dom == 1) iy = cfirst;
+                else iz = cfirst;
+                float qx = (float)(ix + (ax.step > 0)), qy = (float)(iy + (ay.step > 0)), qz = (float)(iz + (az.step > 0));
+                float anx = plane_alpha(ax, qx), any = plane_alpha(ay, qy), anz = plane_alpha(az, qz);
+                int li = __umul24(__umul24(iz - z0, BY) + (iy - y0), BX) + (ix - x0);
+                const int sx = ax.step, sy = ay.step * BX, sz = az.step * BX * BY;
+                const float yl = t_y[r];
+                float acur = astart;
+                for (int step = 0; step < BX + BY + BZ + 3; ++step) {
+                    const float an = fminf(anx, fminf(any, anz));
+                    const float ae = fminf(an, aend);
+                    atomicAdd(&acc[li], to_fixed(fmaxf(ae - acur, 0.0f) * yl));
+                    if (an >= aend) break;
+                    acur = an;
+                    if (an == anx) {
+                        ix += ax.step;
+                        if (ix < x0 || ix >= x1) break;
+                        li += sx;
+                        qx += (float)ax.step;
+                        anx = plane_alpha(ax, qx);
+                    } else if (an == any) {
+                        iy += ay.step;
+                        if (iy < y0 || iy >= y1) break;
+                        li += sy;
+                        qy += (float)ay.step;
+                        any = plane_alpha(ay, qy);
+                    } else {
+                        iz += az.step;
+                        if (iz < z0 || iz >= z1) break;
+                        li += sz;
+                        qz += (float)az.step;
+                        anz = plane_alpha(az, qz);
+                    }
+                }
+            }
+            __syncthreads();
         }
+        flush_view(acc, NB, BX, BY, 0, inv, own);
+        __syncthreads();
     }
-    __syncthreads();
-    store_brick(vol, acc, v, x0, y0, z0, beta);
+    store_owned(vol, own, v, x0, y0, z0, beta);
 }
+
+constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;   // interpolated accumulator: brick plus a one-voxel halo
+constexpr int INT_SAMPLES = CTMI_BWD_INT_SAMPLES;  // samples per interpolated item
 
 __global__ void __launch_bounds__(256) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab, int view0, int nviews,
-                                                         VolDims v, DetDims det, BrickMap m, float beta, float ds)
+                                                         VolDims v, DetDims det, BrickMap m, float beta, float ds,
+                                                         float bound)
 {
-    __shared__ float acc[BRICK * BRICK * BRICK];
-    for (int i = threadIdx.x; i < BRICK * BRICK * BRICK; i += blockDim.x) acc[i] = 0.0f;
+    // accumulator over voxels [b0 - 1, b1] per axis; the halo takes the
+    // corners that fall outside the brick and is discarded, so every sample
+    // scatters to 8 fixed offsets without per-corner tests
+    __shared__ u64 acc[HX * HY * HZ];
+    __shared__ float t_base[3][256], t_st[3][256], t_y[256];
+    __shared__ int t_j[256], t_n[256], t_pre[256];
+    __shared__ int wsum[4];
+    __shared__ unsigned red;
+    for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0ull;
+    float own[OWN];
+#pragma unroll
+    for (int i = 0; i < OWN; ++i) own[i] = 0.0f;
     int bx, by, bz;
     brick_origin(m, blockIdx.x, bx, by, bz);
-    const int x0 = bx * BRICK, y0 = by * BRICK, z0 = bz * BRICK;
-    const int x1 = min(x0 + BRICK, v.nx), y1 = min(y0 + BRICK, v.ny), z1 = min(z0 + BRICK, v.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
+    const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
     // samples that touch voxels [x0, x1) lie in the open box (x0 - 1, x1) of
     // voxel-centre coordinates
     const float lo[3] = {x0 - 1.0f, y0 - 1.0f, z0 - 1.0f};
     const float hi[3] = {(float)x1, (float)y1, (float)z1};
-    const int b0[3] = {x0, y0, z0}, b1[3] = {x1, y1, z1};
-    __syncthreads();
+    const int hx = x1 - x0, hy = y1 - y0, hz = z1 - z0;   // valid halo-local corner index range [0, h]
+    const int tid = threadIdx.x;
 
     for (int k = 0; k < nviews; ++k) {
         const ViewGeo& g = tab[view0 + k];
         int u0, u1, vv0, vv1;
         if (!footprint(g, lo, hi, det, u0, u1, vv0, vv1)) continue;
+        const float* pk = proj + (int64_t)k * det.nv * det.nu;
+        if (tid == 0) red = 0u;
+        __syncthreads();
+        const float maxy = footprint_max(pk, det, u0, u1, vv0, vv1, &red);
+        if (!(maxy > 0.0f)) continue;
+        float inv;
+        const float scale = fixed_scale(bound, maxy, &inv);
         const int w = u1 - u0 + 1;
         const int npx = w * (vv1 - vv0 + 1);
-        const float* pk = proj + (int64_t)k * det.nv * det.nu;
-        for (int p = threadIdx.x; p < npx; p += blockDim.x) {
-            const int r = p / w;
-            const int iv = vv0 + r, iu = u0 + (p - r * w);
-            InterpRay ray;
-            if (!interp_ray(g, iu, iv, v, ds, ray)) continue;
-            // sample range inside the brick's box, widened by one sample each
-            // side; exact membership is decided per corner below
-            float kmin = -CTMI_INF, kmax = CTMI_INF;
-            bool inside = true;
+        for (int p0 = 0; p0 < npx; p0 += 256) {
+            const int p = p0 + tid;
+            int cnt = 0;
+            if (p < npx) {
+                const int r = p / w;
+                const int iv = vv0 + r, iu = u0 + (p - r * w);
+                InterpRay ray;
+                if (interp_ray(g, iu, iv, v, ds, ray)) {
+                    float kmin = -CTMI_INF, kmax = CTMI_INF;
+                    bool inside = true;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (ray.st[a] != 0.0f) {
-                    const float inv = 1.0f / ray.st[a];
-                    const float ka = (lo[a] - ray.Sc[a]) * inv, kb = (hi[a] - ray.Sc[a]) * inv;
-                    kmin = fmaxf(kmin, fminf(ka, kb));
-                    kmax = fminf(kmax, fmaxf(ka, kb));
-                } else {
-                    inside &= ray.Sc[a] > lo[a] && ray.Sc[a] < hi[a];
+                    for (int a = 0; a < 3; ++a) {
+                        if (ray.st[a] != 0.0f) {
+                            const float ia = 1.0f / ray.st[a];
+                            const float ka = (lo[a] - ray.Sc[a]) * ia, kb = (hi[a] - ray.Sc[a]) * ia;
+                            kmin = fmaxf(kmin, fminf(ka, kb));
+                            kmax = fminf(kmax, fmaxf(ka, kb));
+                        } else {
+                            inside &= ray.Sc[a] > lo[a] && ray.Sc[a] < hi[a];
+                        }
+                    }
+                    if (inside && kmin < kmax) {
+                        const int ks = max(ray.k0, (int)__builtin_ceilf(kmin));
+                        const int ke = min(ray.k1, (int)__builtin_floorf(kmax));
+                        if (ke >= ks) {
+                            const int n = ke - ks + 1;
+                            cnt = (n + INT_SAMPLES - 1) / INT_SAMPLES;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                t_base[a][tid] = ray.base[a];
+                                t_st[a][tid] = ray.st[a];
+                            }
+                            t_j[tid] = ks - ray.k0;
+                            t_n[tid] = n;
+                            t_y[tid] = pk[(int64_t)iv * det.nu + iu] * ds * scale;
+                        }
+                    }
                 }
             }
-            if (!inside || !(kmin < kmax)) continue;
-            const int ks = max(ray.k0, (int)__builtin_ceilf(kmin) - 1);
-            const int ke = min(ray.k1, (int)__builtin_floorf(kmax) + 1);
-            if (ks > ke) continue;
-            const float yds = pk[(int64_t)iv * det.nu + iu] * ds;
-            for (int q = ks; q <= ke; ++q) {
-                float pos[3];
-                interp_pos(ray, q, pos);
-                int j0[3];
-                float f[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float fl = __builtin_floorf(pos[a]);
-                    j0[a] = (int)fl;
-                    f[a] = pos[a] - fl;
-                }
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int jx = j0[0] + (c & 1), jy = j0[1] + ((c >> 1) & 1), jz = j0[2] + (c >> 2);
-                    if (jx < b0[0] || jx >= b1[0] || jy < b0[1] || jy >= b1[1] || jz < b0[2] || jz >= b1[2]) continue;
-                    const float wx = (c & 1) ? f[0] : 1.0f - f[0];
-                    const float wy = ((c >> 1) & 1) ? f[1] : 1.0f - f[1];
-                    const float wz = (c >> 2) ? f[2] : 1.0f - f[2];
-                    atomicAdd(&acc[((jz - z0) * BRICK + (jy - y0)) * BRICK + (jx - x0)], wx * wy * wz * yds);
+            int total;
+            const int off = block_scan(cnt, wsum, &total);
+            t_pre[tid] = off;
+            __syncthreads();
+            for (int it = tid; it < total; it += 256) {
+                const int r = owner(t_pre, it);
+                const int q = it - t_pre[r];
+                const int j0 = t_j[r] + q * INT_SAMPLES;
+                const int cntq = min(INT_SAMPLES, t_n[r] - q * INT_SAMPLES);
+                const float bxr = t_base[0][r], byr = t_base[1][r], bzr = t_base[2][r];
+                const float sxr = t_st[0][r], syr = t_st[1][r], szr = t_st[2][r];
+                const float yv = t_y[r];
+                for (int qq = 0; qq < cntq; ++qq) {
+                    // same FP32 position as the forward kernel's sample k
+                    const float j = (float)(j0 + qq);
+                    const float px = __builtin_fmaf(j, sxr, bxr);
+                    const float py = __builtin_fmaf(j, syr, byr);
+                    const float pz = __builtin_fmaf(j, szr, bzr);
+                    const float fx = __builtin_floorf(px), fy = __builtin_floorf(py), fz = __builtin_floorf(pz);
+                    // halo-local index of the lower corner, in [0, h] for samples in the box
+                    int lx = (int)fx - (x0 - 1), ly = (int)fy - (y0 - 1), lz = (int)fz - (z0 - 1);
+                    const bool ok = (unsigned)lx <= (unsigned)hx && (unsigned)ly <= (unsigned)hy &&
+                                    (unsigned)lz <= (unsigned)hz;
+                    lx = min(max(lx, 0), hx);
+                    ly = min(max(ly, 0), hy);
+                    lz = min(max(lz, 0), hz);
+                    const float ax_ = px - fx, ay_ = py - fy, az_ = pz - fz;
+                    const float yz1 = ok ? az_ * yv : 0.0f;
+                    const float yz0 = ok ? (1.0f - az_) * yv : 0.0f;
+                    const float w00 = (1.0f - ay_) * yz0, w10 = ay_ * yz0;
+                    const float w01 = (1.0f - ay_) * yz1, w11 = ay_ * yz1;
+                    const float bx0 = 1.0f - ax_;
+                    u64* a0 = acc + __umul24(__umul24(lz, HY) + ly, HX) + lx;
+                    atomicAdd(a0, to_fixed(bx0 * w00));
+                    atomicAdd(a0 + 1, to_fixed(ax_ * w00));
+                    atomicAdd(a0 + HX, to_fixed(bx0 * w10));
+                    atomicAdd(a0 + HX + 1, to_fixed(ax_ * w10));
+                    atomicAdd(a0 + HX * HY, to_fixed(bx0 * w01));
+                    atomicAdd(a0 + HX * HY + 1, to_fixed(ax_ * w01));
+                    atomicAdd(a0 + HX * HY + HX, to_fixed(bx0 * w11));
+                    atomicAdd(a0 + HX * HY + HX + 1, to_fixed(ax_ * w11));
                 }
             }
+            __syncthreads();
         }
+        flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
+        __syncthreads();
     }
-    __syncthreads();
-    store_brick(vol, acc, v, x0, y0, z0, beta);
+    store_owned(vol, own, v, x0, y0, z0, beta);
 }
 
 BrickMap brick_map(const Plan& p)
 {
     BrickMap m;
-    m.nbx = (p.vol.nx + BRICK - 1) / BRICK;
-    m.nby = (p.vol.ny + BRICK - 1) / BRICK;
-    m.nbz = (p.vol.nz + BRICK - 1) / BRICK;
+    m.nbx = (p.vol.nx + BX - 1) / BX;
+    m.nby = (p.vol.ny + BY - 1) / BY;
+    m.nbz = (p.vol.nz + BZ - 1) / BZ;
     return m;
 }
 
@@ -244,7 +487,7 @@ hipError_t launch_backward_siddon(const Plan& p, const float* proj, float* vol, 
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_siddon, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta);
+                       (int)nviews, p.vol, p.det, m, beta, p.bound_siddon);
     return hipGetLastError();
 }
 
@@ -254,7 +497,7 @@ hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, 
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.ds);
+                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.bound_interp);
     return hipGetLastError();
 }
 

@@ -239,6 +239,28 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     p->det.nv = (int)geo->nDetector[0];
     p->det.nu = (int)geo->nDetector[1];
     p->ds = (float)(geo->accuracy * std::fmin(geo->dVoxel[0], std::fmin(geo->dVoxel[1], geo->dVoxel[2])));
+    // bounds on sum_i |a_ij| over the rays of one view, used to size the
+    // adjoints' fixed-point accumulators: (max matrix entry) x (max number of
+    // pixel centres whose ray meets the cell, or the trilinear support cube)
+    {
+        double half2 = 0.0, off2 = 0.0, hdiag2 = 0.0, hmax = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double h = 0.5 * (double)geo->nVoxel[a] * geo->dVoxel[a];
+            half2 += h * h;
+            off2 += geo->offOrigin[a] * geo->offOrigin[a];
+            hdiag2 += geo->dVoxel[a] * geo->dVoxel[a];
+            hmax = std::fmax(hmax, geo->dVoxel[a]);
+        }
+        const double R = std::sqrt(half2) + std::sqrt(off2);
+        const double Umin = geo->DSO - R - hmax;
+        const double mag = geo->DSD / Umin * (1.0 + (R + hmax) / Umin);
+        const double hdiag = std::sqrt(hdiag2);
+        auto nrays = [&](double ext) {
+            return (std::floor(ext * mag / geo->dDetector[1]) + 2.0) * (std::floor(ext * mag / geo->dDetector[0]) + 2.0);
+        };
+        p->bound_siddon = (float)(hdiag * nrays(hdiag));
+        p->bound_interp = (float)((2.0 * hdiag + (double)p->ds) * nrays(2.0 * hdiag));
+    }
     int L = 1, logL = 0;
     while (L < 2 * p->det.nu - 1 || L < 2) {
         L <<= 1;

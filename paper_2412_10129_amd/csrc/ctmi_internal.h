@@ -53,6 +53,8 @@ struct Plan {
     VolDims vol;
     DetDims det;
     float ds;             // interpolated-projector step, mm
+    float bound_siddon;   // bound on sum_i |a_ij| over the rays of one view, Siddon (mm)
+    float bound_interp;   // the same for the interpolated projector (mm)
 };
 
 // ------------------------------------------------------------ launchers

@@ -1,155 +1,474 @@
 // Forward projectors A (the linear model A x = b of section 2.1): one thread
-// per detector pixel, projection-major ray tiles.
+// per detector pixel, projection-major ray tiles, LDS-staged volume slabs.
 //
-// Work decomposition: a workgroup of 256 threads owns a 16x16 pixel tile of
-// one view; each wavefront covers an 8x8 sub-tile so the 64 rays of a wave
-// travel through neighbouring voxels together.  Blocks are ordered
-// (tile row, view, tile column): the workgroups in flight at any moment
+// A workgroup of 256 threads owns a 32x8 pixel tile of one view.  The tile's
+// rays run mostly along one axis (the dominant axis of the tile's central
+// ray); the volume is cut into slabs of SLAB cells across that axis and the
+// workgroup visits the slabs in the direction of travel.  For each slab it
+// stages in LDS the box of voxels the tile's rays can touch there (bounded by
+// the four corner rays of the tile, which enclose the whole ray bundle), then
+// every thread advances its own ray through the slab reading the volume from
+// LDS.  Global reads are coalesced box loads instead of per-sample gathers
+// from scattered cache lines.  A sample whose voxels fall outside the staged
+// box (box clipped to the LDS capacity, rounding at the box edge) reads them
+// from global memory, so the result never depends on the box estimate.
+//
+// Blocks are ordered (tile row, view, tile column): the workgroups in flight
 // share one detector row band, hence one z-slab of the volume, across many
-// views -- that slab stays resident in L2 / Infinity Cache while the views
-// stream past it.  Detector writes are one float per ray.
+// views.
 #include "ctmi_internal.h"
 
 namespace ctmi {
 
 namespace {
 
-constexpr int TILE = 16;
+#ifndef CTMI_FWD_TU
+#define CTMI_FWD_TU 32
+#endif
+#ifndef CTMI_FWD_TV
+#define CTMI_FWD_TV 8
+#endif
+#ifndef CTMI_FWD_SLAB
+#define CTMI_FWD_SLAB 8
+#endif
+#ifndef CTMI_FWD_BOXCAP
+#define CTMI_FWD_BOXCAP 6144
+#endif
+constexpr int TU = CTMI_FWD_TU, TV = CTMI_FWD_TV;   // ray tile (pixels), TU * TV = 256
+constexpr int SLAB = CTMI_FWD_SLAB;                 // slab thickness along the dominant axis
+constexpr int BOXCAP = CTMI_FWD_BOXCAP;             // LDS floats for the staged box
+static_assert(TU * TV == 256, "one ray per thread");
+static_assert(BOXCAP < 65536, "box index must stay below 2^16");
 
 struct TileMap {
     int tiles_u, tiles_v;
     int64_t nviews;
 };
 
-__device__ __forceinline__ void tile_pixel(const TileMap& m, int64_t b, int& view, int& iu, int& iv)
+// Staged box: voxel index origin and extent per axis (x, y, z); LDS layout
+// [z][y][x] with x fastest (coalesced global loads).
+struct Box {
+    int o[3];
+    int e[3];
+};
+
+__device__ __forceinline__ void tile_of_block(const TileMap& m, int64_t b, int& view, int& tu0, int& tv0)
 {
     const int64_t per_row = m.nviews * m.tiles_u;
     const int tv = (int)(b / per_row);
     const int64_t rem = b - (int64_t)tv * per_row;
     view = (int)(rem / m.tiles_u);
     const int tu = (int)(rem - (int64_t)view * m.tiles_u);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    iu = tu * TILE + (w & 1) * 8 + (lane & 7);
-    iv = tv * TILE + (w >> 1) * 8 + (lane >> 3);
+    tu0 = tu * TU;
+    tv0 = tv * TV;
 }
+
+// Dominant axis and travel direction of the tile's central ray (uniform).
+__device__ __forceinline__ void tile_axis(const ViewGeo& g, const DetDims& det, int tu0, int tv0, int& a, int& dir)
+{
+    const float uc = (float)tu0 + 0.5f * (float)(min(TU, det.nu - tu0) - 1);
+    const float vc = (float)tv0 + 0.5f * (float)(min(TV, det.nv - tv0) - 1);
+    float dc[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dc[i] = g.P00[i] + uc * g.DU[i] + vc * g.DV[i] - g.S[i];
+    const float ax = fabsf(dc[0]), ay = fabsf(dc[1]), az = fabsf(dc[2]);
+    a = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    dir = dc[a] >= 0.0f ? 1 : -1;
+}
+
+// Bounds along the two non-dominant axes of the tile's ray bundle between
+// planes pa0 and pa1 of axis a, in coordinates shifted by `shift` (0 for
+// voxel-cell coordinates, 0.5 for voxel-centre coordinates).
+__device__ __forceinline__ void bundle_bounds(const ViewGeo& g, const DetDims& det, int tu0, int tv0, int a,
+                                              float pa0, float pa1, float shift, float lo[3], float hi[3])
+{
+    const int iu1 = min(tu0 + TU, det.nu) - 1, iv1 = min(tv0 + TV, det.nv) - 1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        lo[i] = CTMI_INF;
+        hi[i] = -CTMI_INF;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float S[3], d[3];
+        pixel_ray(g, (c & 1) ? iu1 : tu0, (c & 2) ? iv1 : tv0, S, d);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) S[i] -= shift;
+        const float inv = 1.0f / d[a];
+#pragma unroll
+        for (int pl = 0; pl < 2; ++pl) {
+            const float t = ((pl ? pa1 : pa0) - S[a]) * inv;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float x = __builtin_fmaf(t, d[i], S[i]);
+                lo[i] = fminf(lo[i], x);
+                hi[i] = fmaxf(hi[i], x);
+            }
+        }
+    }
+}
+
+// Box covering index range [lo_i, hi_i] per axis, clipped to [clo_i, chi_i]
+// and to the LDS capacity (the non-dominant axes shrink first).  Returns
+// false if empty.
+__device__ __forceinline__ bool make_box(const int lo[3], const int hi[3], const int clo[3], const int chi[3], int a,
+                                         Box& b)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int l = max(lo[i], clo[i]), h = min(hi[i], chi[i]);
+        if (h < l) return false;
+        b.o[i] = l;
+        b.e[i] = h - l + 1;
+    }
+    // capacity: shrink the largest non-dominant extent until the box fits
+    for (int it = 0; it < 4 && b.e[0] * b.e[1] * b.e[2] > BOXCAP; ++it) {
+        const int i1 = a == 0 ? 1 : 0, i2 = a == 2 ? 1 : 2;
+        const int i = b.e[i1] >= b.e[i2] ? i1 : i2;
+        const int other = b.e[0] * b.e[1] * b.e[2] / b.e[i];
+        b.e[i] = max(1, BOXCAP / other);
+    }
+    return b.e[0] * b.e[1] * b.e[2] <= BOXCAP;
+}
+
+// Flat loop over the box with x fastest (coalesced global reads).  The
+// index is split into (x, y, z) with float reciprocals: floor((i + 1/2) r),
+// r = fl(1/e), equals i / e for every i < 2^22, because (i + 1/2)/e is at
+// least 1/(2e) away from an integer while the FP32 error is below
+// (i + 1/2) 2^-23 / e.
+__device__ __forceinline__ void load_box(float* box, const float* __restrict__ vol, const VolDims& v, const Box& b)
+{
+    const int n = b.e[0] * b.e[1] * b.e[2];
+    const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int r = (int)__builtin_floorf(((float)i + 0.5f) * r0);
+        const int lx = i - r * b.e[0];
+        const int lz = (int)__builtin_floorf(((float)r + 0.5f) * r1);
+        const int ly = r - lz * b.e[1];
+        const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = b.o[2] + lz;
+        float val = 0.0f;
+        if ((unsigned)gx < (unsigned)v.nx && (unsigned)gy < (unsigned)v.ny && (unsigned)gz < (unsigned)v.nz)
+            val = vol[((int64_t)gz * v.ny + gy) * v.nx + gx];
+        box[i] = val;
+    }
+}
+
+// ------------------------------------------------------------------ Siddon
+struct SiddonWalk {
+    int ix, iy, iz, idx;
+    float qx, qy, qz, anx, any, anz, acur, amax, acc;
+    int left;  // iteration budget
+    bool alive;
+};
 
 __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict__ vol, float* __restrict__ proj,
                                                         const ViewGeo* __restrict__ tab, int view0, TileMap m,
                                                         VolDims v, DetDims det)
 {
-    int view, iu, iv;
-    tile_pixel(m, blockIdx.x, view, iu, iv);
-    if (iu >= det.nu || iv >= det.nv) return;
+    __shared__ float box[BOXCAP];
+    int view, tu0, tv0;
+    tile_of_block(m, blockIdx.x, view, tu0, tv0);
+    const int iu = tu0 + (int)(threadIdx.x % TU), iv = tv0 + (int)(threadIdx.x / TU);
+    const bool active = iu < det.nu && iv < det.nv;
     const ViewGeo& g = tab[view0 + view];
 
     float S[3], d[3];
-    pixel_ray(g, iu, iv, S, d);
+    pixel_ray(g, active ? iu : 0, active ? iv : 0, S, d);
     const float L = world_length(d, v);
     const SiddonAxis ax = siddon_axis(S[0], d[0]);
     const SiddonAxis ay = siddon_axis(S[1], d[1]);
     const SiddonAxis az = siddon_axis(S[2], d[2]);
-    float amin = 0.0f, amax = 1.0f;
-    bool hit = slab_clip(ax, S[0], 0.0f, (float)v.nx, amin, amax);
-    hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, amax);
-    hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, amax);
-    float acc = 0.0f;
-    if (hit && amin < amax) {
-        int ix = entry_cell(S[0], d[0], amin, ax.step, 0, v.nx);
-        int iy = entry_cell(S[1], d[1], amin, ay.step, 0, v.ny);
-        int iz = entry_cell(S[2], d[2], amin, az.step, 0, v.nz);
-        // next plane crossed on each axis
-        float qx = (float)(ix + (ax.step > 0)), qy = (float)(iy + (ay.step > 0)), qz = (float)(iz + (az.step > 0));
-        float anx = plane_alpha(ax, qx), any = plane_alpha(ay, qy), anz = plane_alpha(az, qz);
-        const int sx = ax.step, sy = ay.step * v.nx, sz = az.step * v.nx * v.ny;
-        int idx = (iz * v.ny + iy) * v.nx + ix;
-        float acur = amin;
-        const int cap = v.nx + v.ny + v.nz + 3;
-        for (int it = 0; it < cap; ++it) {
-            const float an = fminf(anx, fminf(any, anz));
-            const float ae = fminf(an, amax);
-            acc = __builtin_fmaf(fmaxf(ae - acur, 0.0f), vol[idx], acc);
-            if (an >= amax) break;
-            acur = an;
-            if (an == anx) {
-                ix += ax.step;
-                if ((unsigned)ix >= (unsigned)v.nx) break;
-                idx += sx;
-                qx += (float)ax.step;
-                anx = plane_alpha(ax, qx);
-            } else if (an == any) {
-                iy += ay.step;
-                if ((unsigned)iy >= (unsigned)v.ny) break;
-                idx += sy;
-                qy += (float)ay.step;
-                any = plane_alpha(ay, qy);
+    SiddonWalk w;
+    w.acc = 0.0f;
+    w.amax = 1.0f;
+    float amin = 0.0f;
+    bool hit = slab_clip(ax, S[0], 0.0f, (float)v.nx, amin, w.amax);
+    hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, w.amax);
+    hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, w.amax);
+    w.alive = active && hit && amin < w.amax;
+    w.ix = entry_cell(S[0], d[0], amin, ax.step, 0, v.nx);
+    w.iy = entry_cell(S[1], d[1], amin, ay.step, 0, v.ny);
+    w.iz = entry_cell(S[2], d[2], amin, az.step, 0, v.nz);
+    w.qx = (float)(w.ix + (ax.step > 0));
+    w.qy = (float)(w.iy + (ay.step > 0));
+    w.qz = (float)(w.iz + (az.step > 0));
+    w.anx = plane_alpha(ax, w.qx);
+    w.any = plane_alpha(ay, w.qy);
+    w.anz = plane_alpha(az, w.qz);
+    w.idx = (w.iz * v.ny + w.iy) * v.nx + w.ix;
+    w.acur = amin;
+    w.left = v.nx + v.ny + v.nz + 3;
+    const int sx = ax.step, sy = ay.step * v.nx, sz = az.step * v.nx * v.ny;
+
+    int a, dir;
+    tile_axis(g, det, tu0, tv0, a, dir);
+    const int na = a == 0 ? v.nx : (a == 1 ? v.ny : v.nz);
+    const int nslab = (na + SLAB - 1) / SLAB;
+    const int clo[3] = {0, 0, 0}, chi[3] = {v.nx - 1, v.ny - 1, v.nz - 1};
+
+    for (int si = 0; si < nslab; ++si) {
+        const int s = dir > 0 ? si : nslab - 1 - si;
+        const int c0 = s * SLAB, c1 = min(c0 + SLAB, na);   // cells [c0, c1) along a
+        float blo[3], bhi[3];
+        bundle_bounds(g, det, tu0, tv0, a, (float)c0, (float)c1, 0.0f, blo, bhi);
+        int lo[3], hi[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = (int)__builtin_floorf(fmaxf(blo[i], -4.0f)) - 1;
+            hi[i] = (int)__builtin_floorf(fminf(bhi[i], 1.0e7f)) + 1;
+        }
+        lo[a] = c0;
+        hi[a] = c1 - 1;
+        Box b;
+        if (!make_box(lo, hi, clo, chi, a, b)) continue;
+        __syncthreads();
+        load_box(box, vol, v, b);
+        __syncthreads();
+        while (w.alive) {
+            const int ia = a == 0 ? w.ix : (a == 1 ? w.iy : w.iz);
+            if (dir > 0 ? ia >= c1 : ia < c0) break;     // the ray has left this slab
+            const int lx = w.ix - b.o[0], ly = w.iy - b.o[1], lz = w.iz - b.o[2];
+            const bool in = (unsigned)lx < (unsigned)b.e[0] && (unsigned)ly < (unsigned)b.e[1] &&
+                            (unsigned)lz < (unsigned)b.e[2];
+            const float val = in ? box[(lz * b.e[1] + ly) * b.e[0] + lx] : vol[w.idx];
+            const float an = fminf(w.anx, fminf(w.any, w.anz));
+            const float ae = fminf(an, w.amax);
+            w.acc = __builtin_fmaf(fmaxf(ae - w.acur, 0.0f), val, w.acc);
+            if (an >= w.amax || --w.left <= 0) {
+                w.alive = false;
+                break;
+            }
+            w.acur = an;
+            if (an == w.anx) {
+                w.ix += ax.step;
+                if ((unsigned)w.ix >= (unsigned)v.nx) w.alive = false;
+                w.idx += sx;
+                w.qx += (float)ax.step;
+                w.anx = plane_alpha(ax, w.qx);
+            } else if (an == w.any) {
+                w.iy += ay.step;
+                if ((unsigned)w.iy >= (unsigned)v.ny) w.alive = false;
+                w.idx += sy;
+                w.qy += (float)ay.step;
+                w.any = plane_alpha(ay, w.qy);
             } else {
-                iz += az.step;
-                if ((unsigned)iz >= (unsigned)v.nz) break;
-                idx += sz;
-                qz += (float)az.step;
-                anz = plane_alpha(az, qz);
+                w.iz += az.step;
+                if ((unsigned)w.iz >= (unsigned)v.nz) w.alive = false;
+                w.idx += sz;
+                w.qz += (float)az.step;
+                w.anz = plane_alpha(az, w.qz);
             }
         }
     }
-    proj[((int64_t)view * det.nv + iv) * det.nu + iu] = acc * L;
+    // anything left (never expected) finishes from global memory
+    while (w.alive) {
+        const float an = fminf(w.anx, fminf(w.any, w.anz));
+        const float ae = fminf(an, w.amax);
+        w.acc = __builtin_fmaf(fmaxf(ae - w.acur, 0.0f), vol[w.idx], w.acc);
+        if (an >= w.amax || --w.left <= 0) break;
+        w.acur = an;
+        if (an == w.anx) {
+            w.ix += ax.step;
+            if ((unsigned)w.ix >= (unsigned)v.nx) break;
+            w.idx += sx;
+            w.qx += (float)ax.step;
+            w.anx = plane_alpha(ax, w.qx);
+        } else if (an == w.any) {
+            w.iy += ay.step;
+            if ((unsigned)w.iy >= (unsigned)v.ny) break;
+            w.idx += sy;
+            w.qy += (float)ay.step;
+            w.any = plane_alpha(ay, w.qy);
+        } else {
+            w.iz += az.step;
+            if ((unsigned)w.iz >= (unsigned)v.nz) break;
+            w.idx += sz;
+            w.qz += (float)az.step;
+            w.anz = plane_alpha(az, w.qz);
+        }
+    }
+    if (active) proj[((int64_t)view * det.nv + iv) * det.nu + iu] = w.acc * L;
 }
 
-// Trilinear sample of the volume at voxel-centre coordinates p, zero outside.
-__device__ __forceinline__ float trilinear(const float* __restrict__ vol, const VolDims& v, const float p[3])
+// ------------------------------------------------------------ interpolated
+__device__ __forceinline__ float lerp1(float a, float r0, float r1) { return __builtin_fmaf(a, r1 - r0, r0); }
+
+// Trilinear sample of the volume at voxel-centre coordinates p, zero outside
+// the grid (out-of-grid corners read as 0, indices clamped so every load is
+// in bounds).  Same lerp sequence as the LDS path, so both give the same bits.
+__device__ __forceinline__ float trilinear_global(const float* __restrict__ vol, const VolDims& v, const float p[3])
 {
     const float fx = __builtin_floorf(p[0]), fy = __builtin_floorf(p[1]), fz = __builtin_floorf(p[2]);
     const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
     const float ax = p[0] - fx, ay = p[1] - fy, az = p[2] - fz;
-    // corner weights are zeroed outside the grid and indices are clamped into
-    // it, so every load stays in bounds whatever the sample position
-    const float wx0 = (unsigned)ix < (unsigned)v.nx ? 1.0f - ax : 0.0f;
-    const float wx1 = (unsigned)(ix + 1) < (unsigned)v.nx ? ax : 0.0f;
-    const float wy0 = (unsigned)iy < (unsigned)v.ny ? 1.0f - ay : 0.0f;
-    const float wy1 = (unsigned)(iy + 1) < (unsigned)v.ny ? ay : 0.0f;
-    const float wz0 = (unsigned)iz < (unsigned)v.nz ? 1.0f - az : 0.0f;
-    const float wz1 = (unsigned)(iz + 1) < (unsigned)v.nz ? az : 0.0f;
-    const int x0 = min(max(ix, 0), v.nx - 1), x1 = min(max(ix + 1, 0), v.nx - 1);
-    const int y0 = min(max(iy, 0), v.ny - 1), y1 = min(max(iy + 1, 0), v.ny - 1);
-    const int z0 = min(max(iz, 0), v.nz - 1), z1 = min(max(iz + 1, 0), v.nz - 1);
-    const int sxy = v.nx * v.ny;
-    const float* r00 = vol + z0 * sxy + y0 * v.nx;
-    const float* r01 = vol + z0 * sxy + y1 * v.nx;
-    const float* r10 = vol + z1 * sxy + y0 * v.nx;
-    const float* r11 = vol + z1 * sxy + y1 * v.nx;
-    const float c00 = __builtin_fmaf(wx0, r00[x0], wx1 * r00[x1]);
-    const float c01 = __builtin_fmaf(wx0, r01[x0], wx1 * r01[x1]);
-    const float c10 = __builtin_fmaf(wx0, r10[x0], wx1 * r10[x1]);
-    const float c11 = __builtin_fmaf(wx0, r11[x0], wx1 * r11[x1]);
-    const float c0 = __builtin_fmaf(wy0, c00, wy1 * c01);
-    const float c1 = __builtin_fmaf(wy0, c10, wy1 * c11);
-    return __builtin_fmaf(wz0, c0, wz1 * c1);
+    float r[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int jx = ix + (c & 1), jy = iy + ((c >> 1) & 1), jz = iz + (c >> 2);
+        const bool in = (unsigned)jx < (unsigned)v.nx && (unsigned)jy < (unsigned)v.ny && (unsigned)jz < (unsigned)v.nz;
+        const int cx = min(max(jx, 0), v.nx - 1), cy = min(max(jy, 0), v.ny - 1), cz = min(max(jz, 0), v.nz - 1);
+        const float val = vol[((int64_t)cz * v.ny + cy) * v.nx + cx];
+        r[c] = in ? val : 0.0f;
+    }
+    const float c00 = lerp1(ax, r[0], r[1]), c01 = lerp1(ax, r[2], r[3]);
+    const float c10 = lerp1(ax, r[4], r[5]), c11 = lerp1(ax, r[6], r[7]);
+    return lerp1(az, lerp1(ay, c00, c01), lerp1(ay, c10, c11));
 }
+
+// Per-tile ray-bundle description in LDS: for each corner ray c and axis i,
+// the coordinate on plane P of the dominant axis is K[c][i] + P * G[c][i].
+struct Bundle {
+    float K[4][3], G[4][3];
+};
 
 __global__ void __launch_bounds__(256) k_forward_interp(const float* __restrict__ vol, float* __restrict__ proj,
                                                         const ViewGeo* __restrict__ tab, int view0, TileMap m,
                                                         VolDims v, DetDims det, float ds)
 {
-    int view, iu, iv;
-    tile_pixel(m, blockIdx.x, view, iu, iv);
-    if (iu >= det.nu || iv >= det.nv) return;
+    __shared__ float box[BOXCAP];
+    __shared__ Bundle bun;
+    int view, tu0, tv0;
+    tile_of_block(m, blockIdx.x, view, tu0, tv0);
+    const int iu = tu0 + (int)(threadIdx.x % TU), iv = tv0 + (int)(threadIdx.x / TU);
+    const bool active = iu < det.nu && iv < det.nv;
     const ViewGeo& g = tab[view0 + view];
-    InterpRay r;
-    float acc = 0.0f;
-    if (interp_ray(g, iu, iv, v, ds, r)) {
-        for (int k = r.k0; k <= r.k1; ++k) {
-            float p[3];
-            interp_pos(r, k, p);
-            acc += trilinear(vol, v, p);
+    int a, dir;
+    tile_axis(g, det, tu0, tv0, a, dir);
+    if (threadIdx.x < 4) {
+        // corner rays of the tile, voxel-centre coordinates
+        const int c = threadIdx.x;
+        const int cu = (c & 1) ? min(tu0 + TU, det.nu) - 1 : tu0, cv = (c & 2) ? min(tv0 + TV, det.nv) - 1 : tv0;
+        float S[3], d[3];
+        pixel_ray(g, cu, cv, S, d);
+        const float inv = 1.0f / d[a];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float Gi = d[i] * inv;
+            bun.G[c][i] = Gi;
+            bun.K[c][i] = (S[i] - 0.5f) - (S[a] - 0.5f) * Gi;
         }
     }
-    proj[((int64_t)view * det.nv + iv) * det.nu + iu] = acc * ds;
+
+    InterpRay r;
+    const bool has = interp_ray(g, active ? iu : 0, active ? iv : 0, v, ds, r) && active;
+    int k = has ? r.k0 : 0;
+    const int k1 = has ? r.k1 : -1;
+    // sample k sits at base + (k - k0) st; along the dominant axis the slab
+    // boundary plane P is reached at (k - k0) = (P - base_a) / st_a
+    const float sa = a == 0 ? r.st[0] : (a == 1 ? r.st[1] : r.st[2]);
+    const float ba = a == 0 ? r.base[0] : (a == 1 ? r.base[1] : r.base[2]);
+    // the slab bookkeeping needs the ray to advance along the tile's direction
+    // (always true for tile-sized bundles); any other ray takes the checked
+    // path in the first slab
+    const bool mono = dir > 0 ? sa > 1e-6f : sa < -1e-6f;
+    const float inv_sa = mono ? 1.0f / sa : 0.0f;
+    float acc = 0.0f;
+    __syncthreads();
+
+    const int na = a == 0 ? v.nx : (a == 1 ? v.ny : v.nz);
+    // a sample's lower corner A = floor(pos_a) lies in [-1, n - 1]; slab s
+    // takes the samples before the plane s SLAB + SLAB - 1 (direction +) or
+    // from the plane s SLAB - 1 on (direction -), and stages planes
+    // [s SLAB - 2, s SLAB + SLAB] so a sample assigned one step early or late
+    // by rounding still finds its corners in the box
+    const int nslab = (na + SLAB) / SLAB;
+    const int clo[3] = {-1, -1, -1}, chi[3] = {v.nx, v.ny, v.nz};
+
+    for (int si = 0; si < nslab; ++si) {
+        const int s = dir > 0 ? si : nslab - 1 - si;
+        const int A0 = s * SLAB - 1, A1 = A0 + SLAB;
+        // bundle bounds over the staged plane range [A0 - 1, A1 + 1]
+        float blo[3] = {CTMI_INF, CTMI_INF, CTMI_INF}, bhi[3] = {-CTMI_INF, -CTMI_INF, -CTMI_INF};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float x0 = __builtin_fmaf((float)(A0 - 1), bun.G[c][i], bun.K[c][i]);
+                const float x1 = __builtin_fmaf((float)(A1 + 1), bun.G[c][i], bun.K[c][i]);
+                blo[i] = fminf(blo[i], fminf(x0, x1));
+                bhi[i] = fmaxf(bhi[i], fmaxf(x0, x1));
+            }
+        int lo[3], hi[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = (int)__builtin_floorf(fmaxf(blo[i], -4.0f)) - 1;
+            hi[i] = (int)__builtin_floorf(fminf(bhi[i], 1.0e7f)) + 2;
+        }
+        lo[a] = A0 - 1;
+        hi[a] = A1 + 1;
+        // this thread's last sample in the slab
+        int kl;
+        {
+            const float P = dir > 0 ? (float)A1 : (float)A0;
+            const float t = (P - ba) * inv_sa;
+            kl = r.k0 + (dir > 0 ? (int)__builtin_ceilf(t) - 1 : (int)__builtin_floorf(t));
+            kl = (si == nslab - 1 || !mono) ? k1 : min(kl, k1);
+        }
+        Box b;
+        const bool fits = make_box(lo, hi, clo, chi, a, b);
+        bool clipped = false;
+        if (fits) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) clipped |= b.o[i] > max(lo[i], clo[i]) || b.o[i] + b.e[i] - 1 < min(hi[i], chi[i]);
+        }
+        __syncthreads();
+        if (fits) load_box(box, vol, v, b);
+        __syncthreads();
+        if (fits && !clipped && mono) {
+            // fast path: every sample of the slab has its 2x2x2 corners in the
+            // box; the byte offset is formed in FP32 from box-relative
+            // coordinates, every intermediate an integer below 2^24
+            const float SY = (float)(4 * b.e[0]), SZ = (float)(4 * b.e[0] * b.e[1]);
+            const float ox = (float)b.o[0], oyf = (float)b.o[1], ozf = (float)b.o[2];
+            const int oy = 4 * b.e[0], oz = 4 * b.e[0] * b.e[1];
+            const char* base = reinterpret_cast<const char*>(box);
+            for (; k <= kl; ++k) {
+                float p[3];
+                interp_pos(r, k, p);
+                const float fx = __builtin_floorf(p[0]), fy = __builtin_floorf(p[1]), fz = __builtin_floorf(p[2]);
+                const int off = (int)__builtin_fmaf(fz - ozf, SZ, __builtin_fmaf(fy - oyf, SY, (fx - ox) * 4.0f));
+                const float* r0 = reinterpret_cast<const float*>(base + off);
+                const float* r1 = reinterpret_cast<const float*>(base + off + oy);
+                const float* r2 = reinterpret_cast<const float*>(base + off + oz);
+                const float* r3 = reinterpret_cast<const float*>(base + off + oz + oy);
+                const float ax = p[0] - fx, ay = p[1] - fy, az = p[2] - fz;
+                const float c00 = lerp1(ax, r0[0], r0[1]), c01 = lerp1(ax, r1[0], r1[1]);
+                const float c10 = lerp1(ax, r2[0], r2[1]), c11 = lerp1(ax, r3[0], r3[1]);
+                acc += lerp1(az, lerp1(ay, c00, c01), lerp1(ay, c10, c11));
+            }
+        } else {
+            for (; k <= kl; ++k) {
+                float p[3];
+                interp_pos(r, k, p);
+                const float fx = __builtin_floorf(p[0]), fy = __builtin_floorf(p[1]), fz = __builtin_floorf(p[2]);
+                const int lx = (int)fx - b.o[0], ly = (int)fy - b.o[1], lz = (int)fz - b.o[2];
+                if (fits && (unsigned)lx < (unsigned)(b.e[0] - 1) && (unsigned)ly < (unsigned)(b.e[1] - 1) &&
+                    (unsigned)lz < (unsigned)(b.e[2] - 1)) {
+                    const float* q = box + (lz * b.e[1] + ly) * b.e[0] + lx;
+                    const int sy = b.e[0], sz = b.e[0] * b.e[1];
+                    const float ax = p[0] - fx, ay = p[1] - fy, az = p[2] - fz;
+                    const float c00 = lerp1(ax, q[0], q[1]), c01 = lerp1(ax, q[sy], q[sy + 1]);
+                    const float c10 = lerp1(ax, q[sz], q[sz + 1]), c11 = lerp1(ax, q[sz + sy], q[sz + sy + 1]);
+                    acc += lerp1(az, lerp1(ay, c00, c01), lerp1(ay, c10, c11));
+                } else {
+                    acc += trilinear_global(vol, v, p);
+                }
+            }
+        }
+    }
+    for (; k <= k1; ++k) {   // anything left (never expected) reads global memory
+        float p[3];
+        interp_pos(r, k, p);
+        acc += trilinear_global(vol, v, p);
+    }
+    if (active) proj[((int64_t)view * det.nv + iv) * det.nu + iu] = acc * ds;
 }
 
 TileMap tile_map(const Plan& p, int64_t nviews)
 {
     TileMap m;
-    m.tiles_u = (p.det.nu + TILE - 1) / TILE;
-    m.tiles_v = (p.det.nv + TILE - 1) / TILE;
+    m.tiles_u = (p.det.nu + TU - 1) / TU;
+    m.tiles_v = (p.det.nv + TV - 1) / TV;
     m.nviews = nviews;
     return m;
 }
