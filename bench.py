@@ -155,39 +155,48 @@ def main():
     kind = args.projector
     x = torch.from_numpy(x_h).to(dev)
     b = torch.from_numpy(y_h).to(dev)
-    # CGLS state
+    # CGLS state (Hestenes-Stiefel): x = 0, r = b, s = A^T b, p = s,
+    # gamma_0 = |s|^2; the scalars live on the device in two rotating rows
+    # [gamma, delta, |r|^2, spare] so every step is a true CGLS iteration.
     from paper_2412_10129_amd import ops
     xs = torch.zeros_like(x)
     r = b.clone()
-    p = x.clone()
-    s = torch.empty_like(x)
+    s = plan.backproject(r, kind=kind)
+    p = s.clone()
     q = torch.empty_like(b)
     ws = ops._ws(dev)
-    sc = torch.ones((2, 4), dtype=torch.float64, device=dev)
-    a = sc.data_ptr()
+    sc = torch.zeros((2, 4), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+
+    def slot(row, col):
+        return sc.data_ptr() + 8 * (4 * row + col)
 
     def dot_into(u, addr):
         ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(u, "u"), ops._ptr(u, "u"), u.numel(), addr, ws.data_ptr(),
                                          ws.numel() * 8, ops._stream()))
 
+    dot_into(s, slot(0, 0))
     ev_f0, ev_f1, ev_b0, ev_b1 = [], [], [], []
+    it = [0]
 
     def step(record=False):
+        cur = it[0] % 2
+        nxt = 1 - cur
         if record:
             e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_f0.append(e)
         plan.forward(p, out=q, kind=kind)
         if record:
             e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_f1.append(e)
-        dot_into(q, a + 8)
-        ops.cgls_xr(xs, p, r, q, a, a + 8, a + 16, ws)
+        dot_into(q, slot(cur, 1))
+        ops.cgls_xr(xs, p, r, q, slot(cur, 0), slot(cur, 1), slot(cur, 2), ws)
         if record:
             e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_b0.append(e)
         plan.backproject(r, out=s, kind=kind)
         if record:
             e = torch.cuda.Event(enable_timing=True); e.record(stream); ev_b1.append(e)
-        dot_into(s, a + 24)
-        ops.cgls_p(p, s, a, a + 24)
+        dot_into(s, slot(nxt, 0))
+        ops.cgls_p(p, s, slot(cur, 0), slot(nxt, 0))
+        it[0] += 1
 
     for _ in range(args.warmup):
         step()
@@ -202,13 +211,17 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the iterate must stay finite (a diverged state would let kernels skip work)
+    h = sc.cpu().numpy()
+    if not (np.all(np.isfinite(h)) and bool(torch.isfinite(xs).all()) and bool(torch.isfinite(r).all())):
+        raise RuntimeError(f"CGLS state is not finite after the timed steps: {h}")
     ms = e0.elapsed_time(e1) / args.steps
     t_fwd = np.mean([a_.elapsed_time(b_) for a_, b_ in zip(ev_f0, ev_f1)])
     t_bwd = np.mean([a_.elapsed_time(b_) for a_, b_ in zip(ev_b0, ev_b1)])
     upd = float(np.prod(geo.nVoxel)) * nviews
     value = 2 * upd / (ms / 1e3)
-    print(f"[bench] {args.steps} steps: {ms:.2f} ms/step (wall {wall:.2f} s); A {t_fwd:.2f} ms, A^T {t_bwd:.2f} ms",
-          flush=True)
+    print(f"[bench] {args.steps} steps: {ms:.2f} ms/step (wall {wall:.2f} s); A {t_fwd:.2f} ms, A^T {t_bwd:.2f} ms; "
+          f"|r|^2 {h[0, 2]:.6g} / {h[1, 2]:.6g}", flush=True)
 
     samples, segments = work_units(geo, nviews)
     units = {"interp_fwd": samples, "interp_bwd": samples, "siddon_fwd": segments, "siddon_bwd": segments}

@@ -132,6 +132,21 @@ def adjoint_voxels(geo: Geometry, angles, proj, iz, iy, ix, kind: str = "siddon"
     return out
 
 
+def gradient_voxels(geo: Geometry, angles, x, y, iz, iy, ix, kind: str = "siddon") -> np.ndarray:
+    """2 (A^T (A x - y))_j for the listed voxels, each term from its
+    definition: the voxel's footprint rays, their full ray sums and the
+    matrix entries a_ij."""
+    angles = _f64(angles)
+    x = _f64(x).reshape(geo.nVoxel)
+    y = _f64(y).reshape((len(angles),) + tuple(geo.nDetector))
+    iz, iy, ix = _i64(iz), _i64(iy), _i64(ix)
+    out = np.zeros(len(iz), dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_gradient_voxels(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(x), _p(y),
+                             ctypes.c_int64(len(iz)), _p(iz), _p(iy), _p(ix), _p(out))
+    return out
+
+
 def dense_matrix(geo: Geometry, angles, kind: str = "siddon") -> np.ndarray:
     """Explicit system matrix, every entry from its definition (tiny sizes)."""
     angles = _f64(angles)
@@ -162,6 +177,18 @@ def bfdk(geo: Geometry, angles, proj) -> np.ndarray:
     out = np.zeros(geo.nVoxel, dtype=np.float64)
     g = _geo(geo)
     _L().orc_bfdk(ctypes.byref(g), _p(angles), ctypes.c_int64(len(angles)), _p(proj), _p(out))
+    return out
+
+
+def bfdk_voxels(geo: Geometry, angles, proj, iz, iy, ix) -> np.ndarray:
+    """The FDK backprojector at the listed voxels only."""
+    angles = _f64(angles)
+    proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
+    iz, iy, ix = _i64(iz), _i64(iy), _i64(ix)
+    out = np.zeros(len(iz), dtype=np.float64)
+    g = _geo(geo)
+    _L().orc_bfdk_voxels(ctypes.byref(g), _p(angles), ctypes.c_int64(len(angles)), _p(proj), ctypes.c_int64(len(iz)),
+                         _p(iz), _p(iy), _p(ix), _p(out))
     return out
 
 

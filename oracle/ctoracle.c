@@ -474,8 +474,21 @@ void orc_interp_adjoint_voxels(const orc_geo* g, const double* angles, int64_t n
                     ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
                     interp_ray_t r;
                     if (!interp_setup(g, S, P, &r)) continue;
+                    /* phi(. - j) vanishes outside the support box: only the
+                     * samples with t_k inside the segment's clip to [bl, bh]
+                     * can contribute (the others are skipped, not approximated) */
+                    double t0 = 0.0, t1 = 1e300;
+                    for (int a = 0; a < 3; ++a) {
+                        if (r.dhat[a] != 0.0) {
+                            const double ta = (bl[a] - r.S[a]) / r.dhat[a], tb = (bh[a] - r.S[a]) / r.dhat[a];
+                            t0 = fmax(t0, fmin(ta, tb));
+                            t1 = fmin(t1, fmax(ta, tb));
+                        }
+                    }
+                    if (!(t0 < t1)) continue;
+                    const int64_t qa = (int64_t)floor(t0 / r.ds) - 1, qb = (int64_t)ceil(t1 / r.ds) + 1;
                     double w = 0.0;
-                    for (int64_t q = r.k0; q <= r.k1; ++q) {
+                    for (int64_t q = qa > r.k0 ? qa : r.k0; q <= (qb < r.k1 ? qb : r.k1); ++q) {
                         const double t = (double)q * r.ds;
                         double phi = 1.0;
                         for (int a = 0; a < 3 && phi > 0.0; ++a) {
@@ -488,6 +501,68 @@ void orc_interp_adjoint_voxels(const orc_geo* g, const double* angles, int64_t n
                 }
         }
         out[i] = acc;
+    }
+}
+
+/* out[i] = 2 (A^T (A x - y))_j for the listed voxels j: for every ray i of
+ * the voxel's footprint with a_ij != 0, the full ray sum (A x)_i minus y_i,
+ * times a_ij (cell chord or tent sum), doubled.  The gradient of
+ * |A x - y|^2 evaluated entry by entry. */
+void orc_gradient_voxels(const orc_geo* g, int kind, const double* angles, int64_t nviews, const double* x,
+                         const double* y, int64_t nsel, const int64_t* iz, const int64_t* iy, const int64_t* ix,
+                         double* out)
+{
+    double lo[3], h[3];
+    int64_t n[3];
+    vol_box(g, lo, h, n);
+    #pragma omp parallel
+    {
+        const int64_t cap = seg_cap(g);
+        int64_t* cell = (int64_t*)malloc(sizeof(int64_t) * cap);
+        double* len = (double*)malloc(sizeof(double) * cap);
+        double* wa = (double*)malloc(sizeof(double) * cap);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < nsel; ++i) {
+            const int64_t j[3] = {ix[i], iy[i], iz[i]};
+            double bl[3], bh[3];
+            for (int a = 0; a < 3; ++a) {
+                const double pad = kind == ORC_SIDDON ? 0.0 : 0.5;   /* cell, or tent support */
+                bl[a] = lo[a] + ((double)j[a] - pad) * h[a];
+                bh[a] = lo[a] + ((double)j[a] + 1.0 + pad) * h[a];
+            }
+            double acc = 0.0;
+            for (int64_t k = 0; k < nviews; ++k) {
+                int64_t u0, u1, v0, v1;
+                if (!box_footprint(g, angles[k], bl, bh, &u0, &u1, &v0, &v1)) continue;
+                for (int64_t iv = v0; iv <= v1; ++iv)
+                    for (int64_t iu = u0; iu <= u1; ++iu) {
+                        double S[3], P[3];
+                        ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+                        double a_ij = 0.0;
+                        if (kind == ORC_SIDDON) {
+                            a_ij = box_chord(S, P, bl, bh);
+                        } else {
+                            interp_ray_t r;
+                            if (!interp_setup(g, S, P, &r)) continue;
+                            for (int64_t q = r.k0; q <= r.k1; ++q) {
+                                const double t = (double)q * r.ds;
+                                double phi = 1.0;
+                                for (int a = 0; a < 3 && phi > 0.0; ++a) {
+                                    const double c = (r.S[a] + t * r.dhat[a] - lo[a]) / h[a] - 0.5;
+                                    phi *= fmax(0.0, 1.0 - fabs(c - (double)j[a]));
+                                }
+                                a_ij += phi;
+                            }
+                            a_ij *= r.ds;
+                        }
+                        if (a_ij == 0.0) continue;
+                        const double res = ray_sum(g, kind, S, P, x, cell, len, wa) - y[(k * g->nv + iv) * g->nu + iu];
+                        acc += a_ij * res;
+                    }
+            }
+            out[i] = 2.0 * acc;
+        }
+        free(cell); free(len); free(wa);
     }
 }
 
@@ -579,6 +654,30 @@ void orc_bfdk(const orc_geo* g, const double* angles, int64_t nviews, const doub
                 }
                 vol[lin_index(g, ix, iy, iz)] = acc;
             }
+}
+
+/* The FDK backprojector at the listed voxels only (same definition). */
+void orc_bfdk_voxels(const orc_geo* g, const double* angles, int64_t nviews, const double* proj, int64_t nsel,
+                     const int64_t* iz, const int64_t* iy, const int64_t* ix, double* out)
+{
+    double lo[3], h[3];
+    int64_t n[3];
+    vol_box(g, lo, h, n);
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < nsel; ++i) {
+        const double X = lo[0] + (ix[i] + 0.5) * h[0];
+        const double Y = lo[1] + (iy[i] + 0.5) * h[1];
+        const double Z = lo[2] + (iz[i] + 0.5) * h[2];
+        double acc = 0.0;
+        for (int64_t k = 0; k < nviews; ++k) {
+            const double c = cos(angles[k]), s = sin(angles[k]);
+            const double U = g->DSO - (X * c + Y * s);
+            const double fu = (g->DSD / U * (-X * s + Y * c) - g->ou) / g->du + 0.5 * (double)g->nu - 0.5;
+            const double fv = (g->DSD / U * Z - g->ov) / g->dv + 0.5 * (double)g->nv - 0.5;
+            acc += (g->DSO / U) * (g->DSO / U) * bilinear(g, proj + k * g->nv * g->nu, fu, fv);
+        }
+        out[i] = acc;
+    }
 }
 
 /* Wang redundancy weight for a laterally offset detector (Wang 2002):

@@ -4,9 +4,9 @@
 //
 // Voxel-driven by bricks: a workgroup owns one 16x16x8 brick of output voxels
 // and accumulates it over every view of the call; each voxel has one writer
-// in global memory and no global atomics are used.  Per view, the brick's
-// detector footprint (bounding box of its projected corners) is enumerated
-// in rounds of 256 pixels: each thread re-traces one pixel's ray inside the
+// in global memory and no global atomics are used.  For a group of views, the
+// brick's detector footprints (bounding boxes of its projected corners) are
+// enumerated in rounds of 256 pixels: each thread re-traces one pixel's ray inside the
 // brick, with the same FP32 arithmetic as the forward kernel (shared helpers
 // in ctmi_internal.h), and records it in an LDS ray table; the rays' work is
 // cut into items of bounded size (a few cells or samples), numbered by a
@@ -15,13 +15,14 @@
 //
 // Accumulation is in 64-bit fixed point in LDS: FP32 LDS atomics are
 // serialised on gfx950 (about 0.3 lane-ops per CU clock) while 64-bit
-// integer LDS atomics run about 30x faster.  Per (brick, view) the scale is
-// the largest power of two that keeps the view's total contribution to any
-// voxel below 2^60, from the footprint's max |y| and a geometric bound on
-// sum_i |a_ij| per view, so every FP32 contribution keeps its full precision;
-// after each view the integers are converted (exact power-of-two scaling)
-// into per-thread FP32 registers in view order.  Integer addition is
-// associative, so the result is bit-reproducible.
+// integer LDS atomics run about 30x faster.  Views are taken in groups of 8;
+// per (brick, group) the scale is the largest power of two that keeps every
+// single contribution a_ij y_i within an int32, from the footprints' max |y|
+// and the largest possible matrix entry (a resolution of 2^-31 of the largest
+// contribution, finer than FP32 rounding); the contributions are summed
+// exactly in the 64-bit accumulators, and after each group converted (exact
+// power-of-two scaling) into per-thread FP32 registers in group order.
+// Integer addition is associative, so the result is bit-reproducible.
 #include "ctmi_internal.h"
 
 namespace ctmi {
@@ -124,44 +125,93 @@ __device__ __forceinline__ int owner(const int* pre, int it)
     return lo;
 }
 
-// Fixed-point scale for one (brick, view): the largest power of two s with
-// s * bound * maxy <= 2^60.  Returns s and writes 1/s.
-__device__ __forceinline__ float fixed_scale(float bound, float maxy, float* inv)
+// Fixed-point scale for one (brick, group of views): the largest power of
+// two s with s * cmax * maxy <= 2^31, cmax a bound on a single matrix entry,
+// so every contribution a_ij y_i fits an int32 with 2^-31 of the largest
+// one as resolution.  Returns s and writes 1/s.
+__device__ __forceinline__ float fixed_scale(float cmax, float maxy, float* inv)
 {
     int e;
-    (void)__builtin_frexpf(0x1p60f / (bound * maxy), &e);
+    (void)__builtin_frexpf(0x1p31f / (cmax * maxy), &e);
     e = min(max(e - 1, -120), 120);
     *inv = __builtin_ldexpf(1.0f, -e);
     return __builtin_ldexpf(1.0f, e);
 }
 
-// Two's-complement 64-bit fixed-point value of q (|q| < 2^62): the high word
-// is floor(q / 2^32) and the low word the remainder in [0, 2^32), rounded to
-// FP32 (an error of at most 256 units of 2^-60 of the scale) and clamped
-// below 2^32 so the unsigned conversion is always in range.
+// A contribution q (|q| <= 2^31, already scaled) as a sign-extended 64-bit
+// two's-complement integer (truncated toward zero: a bias below one unit).
+// The 64-bit accumulators then hold the exact sum of up to 2^32 such terms.
 __device__ __forceinline__ u64 to_fixed(float q)
 {
-    const float hi = __builtin_floorf(q * 0x1p-32f);
-    const float lo = fminf(fmaxf(__builtin_fmaf(-hi, 0x1p32f, q), 0.0f), 4294967040.0f);
-    return ((u64)(unsigned)(int)hi << 32) | (u64)(unsigned)lo;
+    const int v = (int)fminf(fmaxf(q, -2147483520.0f), 2147483520.0f);
+    return (u64)(long long)v;
 }
 
-// Max |y| over the footprint pixels [u0, u1] x [v0, v1] of view image pk,
-// reduced over the block (LDS word `red`, as the bits of a non-negative float).
-__device__ __forceinline__ float footprint_max(const float* __restrict__ pk, const DetDims& det, int u0, int u1,
-                                               int v0, int v1, unsigned* red)
+// Views are processed in groups of GV: one fixed-point scale (from the max
+// |y| over the group's footprints) and one flush per group, with the
+// ray-setup rounds running over the group's combined footprint candidates.
+// The group's footprints live in LDS.
+#ifndef CTMI_BWD_GV
+#define CTMI_BWD_GV 8
+#endif
+constexpr int GV = CTMI_BWD_GV;
+
+struct GroupLds {
+    int u0[GV], v0[GV], w[GV], pre[GV + 1];
+    unsigned red;
+};
+
+// Footprints of views [k, k + n) (threads 0..n-1, one view each) and their
+// candidate prefix; returns the candidate total (uniform).
+__device__ __forceinline__ int make_group(GroupLds& G, const ViewGeo* __restrict__ tab, int view0, int k, int n,
+                                          const float lo[3], const float hi[3], const DetDims& det)
 {
-    const int w = u1 - u0 + 1, npx = w * (v1 - v0 + 1);
+    if ((int)threadIdx.x < GV) {
+        const int g = threadIdx.x;
+        int u0 = 0, u1 = -1, v0 = 0, v1 = -1;
+        const bool ok = g < n && footprint(tab[view0 + k + g], lo, hi, det, u0, u1, v0, v1);
+        G.u0[g] = u0;
+        G.v0[g] = v0;
+        G.w[g] = ok ? u1 - u0 + 1 : 1;
+        G.pre[g + 1] = ok ? (u1 - u0 + 1) * (v1 - v0 + 1) : 0;
+    }
+    if (threadIdx.x == 0) G.red = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        G.pre[0] = 0;
+        for (int g = 0; g < GV; ++g) G.pre[g + 1] += G.pre[g];
+    }
+    __syncthreads();
+    return G.pre[GV];
+}
+
+// Candidate c of the group -> view g and pixel (iu, iv).
+__device__ __forceinline__ void group_pixel(const GroupLds& G, int c, int& g, int& iu, int& iv)
+{
+    g = 0;
+#pragma unroll
+    for (int i = 1; i < GV; ++i) g += c >= G.pre[i] ? 1 : 0;
+    const int p = c - G.pre[g];
+    const int r = p / G.w[g];
+    iv = G.v0[g] + r;
+    iu = G.u0[g] + (p - r * G.w[g]);
+}
+
+// Max |y| over the group's footprint pixels (block reduction).
+__device__ __forceinline__ float group_max(GroupLds& G, const float* __restrict__ proj, const DetDims& det, int k,
+                                           int total)
+{
     float m = 0.0f;
-    for (int p = threadIdx.x; p < npx; p += blockDim.x) {
-        const int r = p / w;
-        m = fmaxf(m, fabsf(pk[(int64_t)(v0 + r) * det.nu + u0 + (p - r * w)]));
+    for (int c = threadIdx.x; c < total; c += blockDim.x) {
+        int g, iu, iv;
+        group_pixel(G, c, g, iu, iv);
+        m = fmaxf(m, fabsf(proj[((int64_t)(k + g) * det.nv + iv) * det.nu + iu]));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(red, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) atomicMax(&G.red, __float_as_uint(m));
     __syncthreads();
-    return __uint_as_float(*red);
+    return __uint_as_float(G.red);
 }
 
 // Add the view's fixed-point sums into the owned FP32 registers and clear
@@ -196,15 +246,16 @@ __device__ __forceinline__ void store_owned(float* __restrict__ vol, const float
 constexpr int SID_CELLS = CTMI_BWD_SID_CELLS;   // dominant-axis cells per Siddon item
 
 __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
-                                                         const ViewGeo* __restrict__ tab, int view0, int nviews,
-                                                         VolDims v, DetDims det, BrickMap m, float beta, float bound)
+                                                         const ViewGeo* __restrict__ tab,
+                                                         const ViewGeo64* __restrict__ tab64, int view0, int nviews,
+                                                         VolDims v, DetDims det, BrickMap m, float beta, float cmax)
 {
     __shared__ u64 acc[NB];
     __shared__ float t_S[3][256], t_d[3][256];
     __shared__ float t_a0[256], t_a1[256], t_y[256];
     __shared__ int t_c0[256], t_nc[256], t_pre[256];
     __shared__ int wsum[4];
-    __shared__ unsigned red;
+    __shared__ GroupLds G;
     for (int i = threadIdx.x; i < NB; i += blockDim.x) acc[i] = 0ull;
     float own[OWN];
 #pragma unroll
@@ -213,45 +264,47 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
     brick_origin(m, blockIdx.x, bx, by, bz);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
     const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
-    const int b0[3] = {x0, y0, z0}, b1[3] = {x1, y1, z1};
     const float lo[3] = {x0 - 0.5f, y0 - 0.5f, z0 - 0.5f};   // cell box in voxel-centre coordinates
     const float hi[3] = {x1 - 0.5f, y1 - 0.5f, z1 - 0.5f};
     const int tid = threadIdx.x;
 
-    for (int k = 0; k < nviews; ++k) {
-        const ViewGeo& g = tab[view0 + k];
-        int u0, u1, vv0, vv1;
-        if (!footprint(g, lo, hi, det, u0, u1, vv0, vv1)) continue;
-        const float* pk = proj + (int64_t)k * det.nv * det.nu;
-        if (tid == 0) red = 0u;
+    for (int k = 0; k < nviews; k += GV) {
+        const int ng = min(GV, nviews - k);
         __syncthreads();
-        const float maxy = footprint_max(pk, det, u0, u1, vv0, vv1, &red);
+        const int npx = make_group(G, tab, view0, k, ng, lo, hi, det);
+        if (npx == 0) continue;
+        const float maxy = group_max(G, proj, det, k, npx);
         if (!(maxy > 0.0f)) continue;
         float inv;
-        const float scale = fixed_scale(bound, maxy, &inv);
-        const int w = u1 - u0 + 1;
-        const int npx = w * (vv1 - vv0 + 1);
+        const float scale = fixed_scale(cmax, maxy, &inv);
         for (int p0 = 0; p0 < npx; p0 += 256) {
             const int p = p0 + tid;
             int cnt = 0;
             if (p < npx) {
-                const int r = p / w;
-                const int iv = vv0 + r, iu = u0 + (p - r * w);
-                float S[3], d[3];
-                pixel_ray(g, iu, iv, S, d);
-                const SiddonAxis ax[3] = {siddon_axis(S[0], d[0]), siddon_axis(S[1], d[1]), siddon_axis(S[2], d[2])};
-                float amin = 0.0f, amax = 1.0f;
-                bool hit = slab_clip(ax[0], S[0], (float)x0, (float)x1, amin, amax);
-                hit &= slab_clip(ax[1], S[1], (float)y0, (float)y1, amin, amax);
-                hit &= slab_clip(ax[2], S[2], (float)z0, (float)z1, amin, amax);
-                // the ray's dominant axis (largest |d|, never parallel to its planes)
+                int gv, iu, iv;
+                group_pixel(G, p, gv, iu, iv);
+                const float* pk = proj + (int64_t)(k + gv) * det.nv * det.nu;
+                float S[3], d[3], amin, amax;
+                siddon_ray(tab64[view0 + k + gv], iu, iv, v, S, d, amin, amax);
+                const SiddonAxis ax0 = siddon_axis(S[0], d[0]), ax1 = siddon_axis(S[1], d[1]),
+                                 ax2 = siddon_axis(S[2], d[2]);
+                bool hit = slab_clip(ax0, S[0], (float)x0, (float)x1, amin, amax);
+                hit &= slab_clip(ax1, S[1], (float)y0, (float)y1, amin, amax);
+                hit &= slab_clip(ax2, S[2], (float)z0, (float)z1, amin, amax);
+                // the ray's dominant axis (largest |d|, never parallel to its planes);
+                // selected by value so nothing is indexed at run time
                 const int dom = (fabsf(d[0]) >= fabsf(d[1]) && fabsf(d[0]) >= fabsf(d[2])) ? 0
                                 : (fabsf(d[1]) >= fabsf(d[2]) ? 1 : 2);
                 if (hit && amin < amax) {
+                    const float Sd = dom == 0 ? S[0] : (dom == 1 ? S[1] : S[2]);
+                    const float dd = dom == 0 ? d[0] : (dom == 1 ? d[1] : d[2]);
+                    const int sd = dom == 0 ? ax0.step : (dom == 1 ? ax1.step : ax2.step);
+                    const int lod = dom == 0 ? x0 : (dom == 1 ? y0 : z0);
+                    const int hid = dom == 0 ? x1 : (dom == 1 ? y1 : z1);
                     // dominant-axis cells from entry to exit
-                    const int c0 = entry_cell(S[dom], d[dom], amin, ax[dom].step, b0[dom], b1[dom]);
-                    const int c1 = entry_cell(S[dom], -d[dom], -amax, -ax[dom].step, b0[dom], b1[dom]);
-                    const int nc = (c1 - c0) * ax[dom].step + 1;
+                    const int c0 = entry_cell(Sd, dd, amin, sd, lod, hid);
+                    const int c1 = entry_cell(Sd, -dd, -amax, -sd, lod, hid);
+                    const int nc = (c1 - c0) * sd + 1;
                     if (nc > 0) {
                         cnt = (nc + SID_CELLS - 1) / SID_CELLS;
 #pragma unroll
@@ -280,7 +333,10 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
                 const SiddonAxis ay = siddon_axis(S[1], d[1]);
                 const SiddonAxis az = siddon_axis(S[2], d[2]);
                 const int dom = t_c0[r] & 3, c0 = t_c0[r] >> 2;
-                const SiddonAxis& ad = dom == 0 ? ax : (dom == 1 ? ay : az);
+                SiddonAxis ad;
+                ad.inv = dom == 0 ? ax.inv : (dom == 1 ? ay.inv : az.inv);
+                ad.c = dom == 0 ? ax.c : (dom == 1 ? ay.c : az.c);
+                ad.step = dom == 0 ? ax.step : (dom == 1 ? ay.step : az.step);
                 const int nc = t_nc[r];
                 const int cfirst = c0 + ad.step * q * SID_CELLS;
                 const int clast = c0 + ad.step * min(q * SID_CELLS + SID_CELLS - 1, nc - 1);
@@ -339,10 +395,11 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;   // interpolated accumulator: brick plus a one-voxel halo
 constexpr int INT_SAMPLES = CTMI_BWD_INT_SAMPLES;  // samples per interpolated item
 
-__global__ void __launch_bounds__(256) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
-                                                         const ViewGeo* __restrict__ tab, int view0, int nviews,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
+                                                         const ViewGeo* __restrict__ tab,
+                                                         const ViewGeo64* __restrict__ tab64, int view0, int nviews,
                                                          VolDims v, DetDims det, BrickMap m, float beta, float ds,
-                                                         float bound)
+                                                         float cmax)
 {
     // accumulator over voxels [b0 - 1, b1] per axis; the halo takes the
     // corners that fall outside the brick and is discarded, so every sample
@@ -351,7 +408,7 @@ __global__ void __launch_bounds__(256) k_backward_interp(const float* __restrict
     __shared__ float t_base[3][256], t_st[3][256], t_y[256];
     __shared__ int t_j[256], t_n[256], t_pre[256];
     __shared__ int wsum[4];
-    __shared__ unsigned red;
+    __shared__ GroupLds G;
     for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0ull;
     float own[OWN];
 #pragma unroll
@@ -367,43 +424,41 @@ __global__ void __launch_bounds__(256) k_backward_interp(const float* __restrict
     const int hx = x1 - x0, hy = y1 - y0, hz = z1 - z0;   // valid halo-local corner index range [0, h]
     const int tid = threadIdx.x;
 
-    for (int k = 0; k < nviews; ++k) {
-        const ViewGeo& g = tab[view0 + k];
-        int u0, u1, vv0, vv1;
-        if (!footprint(g, lo, hi, det, u0, u1, vv0, vv1)) continue;
-        const float* pk = proj + (int64_t)k * det.nv * det.nu;
-        if (tid == 0) red = 0u;
+    for (int k = 0; k < nviews; k += GV) {
+        const int ng = min(GV, nviews - k);
         __syncthreads();
-        const float maxy = footprint_max(pk, det, u0, u1, vv0, vv1, &red);
+        const int npx = make_group(G, tab, view0, k, ng, lo, hi, det);
+        if (npx == 0) continue;
+        const float maxy = group_max(G, proj, det, k, npx);
         if (!(maxy > 0.0f)) continue;
         float inv;
-        const float scale = fixed_scale(bound, maxy, &inv);
-        const int w = u1 - u0 + 1;
-        const int npx = w * (vv1 - vv0 + 1);
+        const float scale = fixed_scale(cmax, maxy, &inv);
         for (int p0 = 0; p0 < npx; p0 += 256) {
             const int p = p0 + tid;
             int cnt = 0;
             if (p < npx) {
-                const int r = p / w;
-                const int iv = vv0 + r, iu = u0 + (p - r * w);
+                int gv, iu, iv;
+                group_pixel(G, p, gv, iu, iv);
+                const float* pk = proj + (int64_t)(k + gv) * det.nv * det.nu;
                 InterpRay ray;
-                if (interp_ray(g, iu, iv, v, ds, ray)) {
+                if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, ray)) {
+                    // samples (relative to the anchor kc) inside the brick's box
                     float kmin = -CTMI_INF, kmax = CTMI_INF;
                     bool inside = true;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         if (ray.st[a] != 0.0f) {
                             const float ia = 1.0f / ray.st[a];
-                            const float ka = (lo[a] - ray.Sc[a]) * ia, kb = (hi[a] - ray.Sc[a]) * ia;
+                            const float ka = (lo[a] - ray.base[a]) * ia, kb = (hi[a] - ray.base[a]) * ia;
                             kmin = fmaxf(kmin, fminf(ka, kb));
                             kmax = fminf(kmax, fmaxf(ka, kb));
                         } else {
-                            inside &= ray.Sc[a] > lo[a] && ray.Sc[a] < hi[a];
+                            inside &= ray.base[a] > lo[a] && ray.base[a] < hi[a];
                         }
                     }
                     if (inside && kmin < kmax) {
-                        const int ks = max(ray.k0, (int)__builtin_ceilf(kmin));
-                        const int ke = min(ray.k1, (int)__builtin_floorf(kmax));
+                        const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin));
+                        const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax));
                         if (ke >= ks) {
                             const int n = ke - ks + 1;
                             cnt = (n + INT_SAMPLES - 1) / INT_SAMPLES;
@@ -412,7 +467,7 @@ __global__ void __launch_bounds__(256) k_backward_interp(const float* __restrict
                                 t_base[a][tid] = ray.base[a];
                                 t_st[a][tid] = ray.st[a];
                             }
-                            t_j[tid] = ks - ray.k0;
+                            t_j[tid] = ks - ray.kc;
                             t_n[tid] = n;
                             t_y[tid] = pk[(int64_t)iv * det.nu + iu] * ds * scale;
                         }
@@ -486,8 +541,8 @@ hipError_t launch_backward_siddon(const Plan& p, const float* proj, float* vol, 
 {
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
-    hipLaunchKernelGGL(k_backward_siddon, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.bound_siddon);
+    hipLaunchKernelGGL(k_backward_siddon, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
+                       (int)nviews, p.vol, p.det, m, beta, p.entry_siddon);
     return hipGetLastError();
 }
 
@@ -496,8 +551,8 @@ hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, 
 {
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
-    hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.bound_interp);
+    hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
+                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.entry_interp);
     return hipGetLastError();
 }
 

@@ -86,8 +86,9 @@ int check_geometry(const ctmi_geometry* g, const double* angles, int64_t nviews)
     return CTMI_OK;
 }
 
-// Per-view table in FP64, rounded once to FP32.
-void view_table(const ctmi_geometry* g, const double* angles, int64_t nviews, ViewGeo* out)
+// Per-view table in FP64, rounded once to FP32 (out), and its FP64 ray part (out64, optional).
+void view_table(const ctmi_geometry* g, const double* angles, int64_t nviews, ViewGeo* out,
+                ctmi::ViewGeo64* out64 = nullptr)
 {
     const double nz = (double)g->nVoxel[0], ny = (double)g->nVoxel[1], nx = (double)g->nVoxel[2];
     const double hz = g->dVoxel[0], hy = g->dVoxel[1], hx = g->dVoxel[2];
@@ -112,6 +113,16 @@ void view_table(const ctmi_geometry* g, const double* angles, int64_t nviews, Vi
             o.P00[a] = (float)((P00[a] - lo[a]) / h[a]);
             o.DU[a] = (float)(DU[a] / h[a]);
             o.DV[a] = (float)(DV[a] / h[a]);
+        }
+        if (out64) {
+            ctmi::ViewGeo64& o64 = out64[k];
+            std::memset(&o64, 0, sizeof o64);
+            for (int a = 0; a < 3; ++a) {
+                o64.S[a] = (S[a] - lo[a]) / h[a];
+                o64.P00[a] = (P00[a] - lo[a]) / h[a];
+                o64.DU[a] = DU[a] / h[a];
+                o64.DV[a] = DV[a] / h[a];
+            }
         }
         // world position of voxel centre index c: X = lo + (c + 1/2) h
         const double X0 = lo[0] + 0.5 * hx, Y0 = lo[1] + 0.5 * hy, Z0 = lo[2] + 0.5 * hz;
@@ -239,27 +250,16 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     p->det.nv = (int)geo->nDetector[0];
     p->det.nu = (int)geo->nDetector[1];
     p->ds = (float)(geo->accuracy * std::fmin(geo->dVoxel[0], std::fmin(geo->dVoxel[1], geo->dVoxel[2])));
-    // bounds on sum_i |a_ij| over the rays of one view, used to size the
-    // adjoints' fixed-point accumulators: (max matrix entry) x (max number of
-    // pixel centres whose ray meets the cell, or the trilinear support cube)
+    // largest possible matrix entries, which size the adjoints' fixed-point
+    // scale: a Siddon entry is a chord of one cell (at most its diagonal); an
+    // interpolated entry is ds times the tent sum over the samples inside the
+    // 2x2x2 support (at most 2 diagonal / ds + 1 samples of weight <= 1)
     {
-        double half2 = 0.0, off2 = 0.0, hdiag2 = 0.0, hmax = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            const double h = 0.5 * (double)geo->nVoxel[a] * geo->dVoxel[a];
-            half2 += h * h;
-            off2 += geo->offOrigin[a] * geo->offOrigin[a];
-            hdiag2 += geo->dVoxel[a] * geo->dVoxel[a];
-            hmax = std::fmax(hmax, geo->dVoxel[a]);
-        }
-        const double R = std::sqrt(half2) + std::sqrt(off2);
-        const double Umin = geo->DSO - R - hmax;
-        const double mag = geo->DSD / Umin * (1.0 + (R + hmax) / Umin);
+        double hdiag2 = 0.0;
+        for (int a = 0; a < 3; ++a) hdiag2 += geo->dVoxel[a] * geo->dVoxel[a];
         const double hdiag = std::sqrt(hdiag2);
-        auto nrays = [&](double ext) {
-            return (std::floor(ext * mag / geo->dDetector[1]) + 2.0) * (std::floor(ext * mag / geo->dDetector[0]) + 2.0);
-        };
-        p->bound_siddon = (float)(hdiag * nrays(hdiag));
-        p->bound_interp = (float)((2.0 * hdiag + (double)p->ds) * nrays(2.0 * hdiag));
+        p->entry_siddon = (float)(hdiag * 1.0001);
+        p->entry_interp = (float)((2.0 * hdiag + (double)p->ds) * 1.0001);
     }
     int L = 1, logL = 0;
     while (L < 2 * p->det.nu - 1 || L < 2) {
@@ -270,7 +270,8 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     p->fft_log2 = logL;
 
     std::vector<ViewGeo> t(nviews);
-    view_table(geo, angles, nviews, t.data());
+    std::vector<ctmi::ViewGeo64> t64(nviews);
+    view_table(geo, angles, nviews, t.data(), t64.data());
     std::vector<float> Hbr, tw;
     ramp_tables(geo, L, logL, Hbr, tw);
 
@@ -280,18 +281,21 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
         return hip_fail(e, "hipGetDevice");
     }
     const size_t tb = sizeof(ViewGeo) * (size_t)nviews;
+    const size_t t64b = sizeof(ctmi::ViewGeo64) * (size_t)nviews;
     const size_t hb = sizeof(float) * (size_t)L;
     const size_t wb = sizeof(float) * (size_t)L;  // L/2 float2
     char* mem = nullptr;
-    e = hipMalloc(reinterpret_cast<void**>(&mem), tb + hb + wb);
+    e = hipMalloc(reinterpret_cast<void**>(&mem), tb + t64b + hb + wb);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "hipMalloc(plan tables)");
     }
     p->d_views = reinterpret_cast<ViewGeo*>(mem);
-    p->d_filter = reinterpret_cast<float*>(mem + tb);
-    p->d_twiddle = reinterpret_cast<float2*>(mem + tb + hb);
+    p->d_views64 = reinterpret_cast<ctmi::ViewGeo64*>(mem + tb);
+    p->d_filter = reinterpret_cast<float*>(mem + tb + t64b);
+    p->d_twiddle = reinterpret_cast<float2*>(mem + tb + t64b + hb);
     if ((e = hipMemcpy(p->d_views, t.data(), tb, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_views64, t64.data(), t64b, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_filter, Hbr.data(), hb, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_twiddle, tw.data(), wb, hipMemcpyHostToDevice)) != hipSuccess) {
         (void)hipFree(mem);

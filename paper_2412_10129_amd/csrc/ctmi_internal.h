@@ -31,6 +31,20 @@ struct ViewGeo {
 };
 static_assert(sizeof(ViewGeo) == 128, "view table row must be 128 bytes");
 
+// The same geometry in FP64 (source, pixel (0,0) centre, pixel steps, in
+// voxel-cell coordinates) for the once-per-ray setup: the source lies
+// thousands of voxels from the volume, and FP32 positions that far out carry
+// errors of ~1e-4 voxel, so rays are set up in FP64 and re-anchored next to
+// the volume before the FP32 per-sample loops.
+struct ViewGeo64 {
+    double S[3];
+    double P00[3];
+    double DU[3];
+    double DV[3];
+    double pad[4];
+};
+static_assert(sizeof(ViewGeo64) == 128, "FP64 view table row must be 128 bytes");
+
 struct VolDims {
     int nx, ny, nz;
     float hx, hy, hz;  // voxel size, mm
@@ -46,6 +60,7 @@ struct Plan {
     int64_t nviews;
     int device;
     ViewGeo* d_views;     // [nviews]
+    ViewGeo64* d_views64; // [nviews]
     float* d_filter;      // [fft_len] Ram-Lak response, bit-reversed order, 1/L folded in
     float2* d_twiddle;    // [fft_len / 2] exp(-2 pi i k / L)
     int fft_len;
@@ -53,8 +68,8 @@ struct Plan {
     VolDims vol;
     DetDims det;
     float ds;             // interpolated-projector step, mm
-    float bound_siddon;   // bound on sum_i |a_ij| over the rays of one view, Siddon (mm)
-    float bound_interp;   // the same for the interpolated projector (mm)
+    float entry_siddon;   // largest possible matrix entry a_ij, Siddon (mm)
+    float entry_interp;   // the same for the interpolated projector (mm)
 };
 
 // ------------------------------------------------------------ launchers
@@ -162,52 +177,96 @@ __device__ __forceinline__ int entry_cell(float S, float d, float a, int step, i
     return i;
 }
 
-// --- interpolated ----------------------------------------------------------
-// Samples of the ray in voxel-centre coordinates: pos_k = base + (k - k0) st,
-// k0..k1 the samples inside the open box (-1, n) where the trilinear
-// interpolant can be nonzero.  `ds` is the step in mm.
-struct InterpRay {
-    float Sc[3];   // source, voxel-centre coordinates
-    float st[3];   // step per sample, voxel units
-    float base[3]; // position of sample k0
-    int k0, k1;
-};
-
-__device__ __forceinline__ bool interp_ray(const ViewGeo& g, int iu, int iv, const VolDims& v, float ds,
-                                           InterpRay& r)
+// FP64 source and direction of the ray through the centre of pixel (iu, iv).
+__device__ __forceinline__ void pixel_ray64(const ViewGeo64& g, int iu, int iv, double S[3], double d[3])
 {
-    float S[3], d[3];
-    pixel_ray(g, iu, iv, S, d);
-    const float L = world_length(d, v);
-    const float scale = ds / L;
-    const int n[3] = {v.nx, v.ny, v.nz};
-    float kmin = 0.0f, kmax = L / ds;
+    const double fu = (double)iu, fv = (double)iv;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        r.Sc[a] = S[a] - 0.5f;
-        r.st[a] = d[a] * scale;
-        if (r.st[a] != 0.0f) {
-            const float inv = 1.0f / r.st[a];
-            const float ka = (-1.0f - r.Sc[a]) * inv;
-            const float kb = ((float)n[a] - r.Sc[a]) * inv;
-            kmin = fmaxf(kmin, fminf(ka, kb));
-            kmax = fminf(kmax, fmaxf(ka, kb));
-        } else if (!(r.Sc[a] > -1.0f && r.Sc[a] < (float)n[a])) {
+        S[a] = g.S[a];
+        d[a] = __builtin_fma(fv, g.DV[a], __builtin_fma(fu, g.DU[a], g.P00[a])) - g.S[a];
+    }
+}
+
+// Siddon ray X(alpha) = S + alpha d re-anchored at the point of the line
+// closest to the volume centre, so that the FP32 plane crossings
+// alpha = (q - S) / d are formed from small numbers.  The source -> pixel
+// segment is alpha in [a_lo, a_hi].  Forward and adjoint kernels both set up
+// rays here.
+__device__ __forceinline__ void siddon_ray(const ViewGeo64& g, int iu, int iv, const VolDims& v, float S[3],
+                                           float d[3], float& a_lo, float& a_hi)
+{
+    double Sd[3], dd[3];
+    pixel_ray64(g, iu, iv, Sd, dd);
+    const double c[3] = {0.5 * v.nx, 0.5 * v.ny, 0.5 * v.nz};
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        num = __builtin_fma(c[a] - Sd[a], dd[a], num);
+        den = __builtin_fma(dd[a], dd[a], den);
+    }
+    const double t0 = num / den;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        S[a] = (float)__builtin_fma(t0, dd[a], Sd[a]);
+        d[a] = (float)dd[a];
+    }
+    a_lo = (float)(-t0);
+    a_hi = (float)(1.0 - t0);
+}
+
+// --- interpolated ----------------------------------------------------------
+// Samples of the ray in voxel-centre coordinates: sample k is at
+// base + (k - kc) st, kc the middle sample of k0..k1, the samples inside the
+// open box (-1, n) where the trilinear interpolant can be nonzero.  The
+// setup (clip, sample range, anchor) is FP64; base and st are rounded once.
+struct InterpRay {
+    float st[3];   // step per sample, voxel units
+    float base[3]; // position of sample kc
+    int kc, k0, k1;
+};
+
+__device__ __forceinline__ bool interp_ray(const ViewGeo64& g, int iu, int iv, const VolDims& v, float ds,
+                                           InterpRay& r)
+{
+    double S[3], d[3];
+    pixel_ray64(g, iu, iv, S, d);
+    const double x = d[0] * v.hx, y = d[1] * v.hy, z = d[2] * v.hz;
+    const double L = __builtin_sqrt(__builtin_fma(x, x, __builtin_fma(y, y, z * z)));
+    const double sc = (double)ds / L;
+    const int n[3] = {v.nx, v.ny, v.nz};
+    double kmin = 0.0, kmax = L / (double)ds;
+    double Sc[3], st[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Sc[a] = S[a] - 0.5;
+        st[a] = d[a] * sc;
+        if (st[a] != 0.0) {
+            const double inv = 1.0 / st[a];
+            const double ka = (-1.0 - Sc[a]) * inv;
+            const double kb = ((double)n[a] - Sc[a]) * inv;
+            kmin = fmax(kmin, fmin(ka, kb));
+            kmax = fmin(kmax, fmax(ka, kb));
+        } else if (!(Sc[a] > -1.0 && Sc[a] < (double)n[a])) {
             return false;
         }
     }
     if (!(kmin < kmax)) return false;
-    r.k0 = (int)__builtin_ceilf(kmin);
-    r.k1 = (int)__builtin_floorf(kmax);
-    const float fk0 = (float)r.k0;
+    r.k0 = (int)__builtin_ceil(kmin);
+    r.k1 = (int)__builtin_floor(kmax);
+    if (r.k1 < r.k0) return false;
+    r.kc = (r.k0 + r.k1) >> 1;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) r.base[a] = __builtin_fmaf(fk0, r.st[a], r.Sc[a]);
-    return r.k1 >= r.k0;
+    for (int a = 0; a < 3; ++a) {
+        r.st[a] = (float)st[a];
+        r.base[a] = (float)__builtin_fma((double)r.kc, st[a], Sc[a]);
+    }
+    return true;
 }
 
 __device__ __forceinline__ void interp_pos(const InterpRay& r, int k, float p[3])
 {
-    const float j = (float)(k - r.k0);
+    const float j = (float)(k - r.kc);
 #pragma unroll
     for (int a = 0; a < 3; ++a) p[a] = __builtin_fmaf(j, r.st[a], r.base[a]);
 }

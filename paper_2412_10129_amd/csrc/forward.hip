@@ -23,10 +23,10 @@ namespace ctmi {
 namespace {
 
 #ifndef CTMI_FWD_TU
-#define CTMI_FWD_TU 32
+#define CTMI_FWD_TU 16
 #endif
 #ifndef CTMI_FWD_TV
-#define CTMI_FWD_TV 8
+#define CTMI_FWD_TV 16
 #endif
 #ifndef CTMI_FWD_SLAB
 #define CTMI_FWD_SLAB 8
@@ -121,12 +121,21 @@ __device__ __forceinline__ bool make_box(const int lo[3], const int hi[3], const
         b.o[i] = l;
         b.e[i] = h - l + 1;
     }
-    // capacity: shrink the largest non-dominant extent until the box fits
+    // capacity: shrink the larger non-dominant extent until the box fits
+    // (every index below is a compile-time constant, so the box stays in
+    // registers)
     for (int it = 0; it < 4 && b.e[0] * b.e[1] * b.e[2] > BOXCAP; ++it) {
-        const int i1 = a == 0 ? 1 : 0, i2 = a == 2 ? 1 : 2;
-        const int i = b.e[i1] >= b.e[i2] ? i1 : i2;
-        const int other = b.e[0] * b.e[1] * b.e[2] / b.e[i];
-        b.e[i] = max(1, BOXCAP / other);
+        const int e1 = a == 0 ? b.e[1] : b.e[0];      // first non-dominant extent
+        const int e2 = a == 2 ? b.e[1] : b.e[2];      // second non-dominant extent
+        const bool first = e1 >= e2;
+        const int keep = first ? e2 : e1;             // the other non-dominant extent
+        const int ea = a == 0 ? b.e[0] : (a == 1 ? b.e[1] : b.e[2]);
+        const int ne = max(1, BOXCAP / (keep * ea));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const bool is1 = i == (a == 0 ? 1 : 0), is2 = i == (a == 2 ? 1 : 2);
+            if ((first && is1) || (!first && is2)) b.e[i] = ne;
+        }
     }
     return b.e[0] * b.e[1] * b.e[2] <= BOXCAP;
 }
@@ -162,7 +171,8 @@ struct SiddonWalk {
 };
 
 __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict__ vol, float* __restrict__ proj,
-                                                        const ViewGeo* __restrict__ tab, int view0, TileMap m,
+                                                        const ViewGeo* __restrict__ tab,
+                                                        const ViewGeo64* __restrict__ tab64, int view0, TileMap m,
                                                         VolDims v, DetDims det)
 {
     __shared__ float box[BOXCAP];
@@ -172,16 +182,16 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
     const bool active = iu < det.nu && iv < det.nv;
     const ViewGeo& g = tab[view0 + view];
 
-    float S[3], d[3];
-    pixel_ray(g, active ? iu : 0, active ? iv : 0, S, d);
+    float S[3], d[3], a_lo, a_hi;
+    siddon_ray(tab64[view0 + view], active ? iu : 0, active ? iv : 0, v, S, d, a_lo, a_hi);
     const float L = world_length(d, v);
     const SiddonAxis ax = siddon_axis(S[0], d[0]);
     const SiddonAxis ay = siddon_axis(S[1], d[1]);
     const SiddonAxis az = siddon_axis(S[2], d[2]);
     SiddonWalk w;
     w.acc = 0.0f;
-    w.amax = 1.0f;
-    float amin = 0.0f;
+    w.amax = a_hi;
+    float amin = a_lo;
     bool hit = slab_clip(ax, S[0], 0.0f, (float)v.nx, amin, w.amax);
     hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, w.amax);
     hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, w.amax);
@@ -217,8 +227,11 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
             lo[i] = (int)__builtin_floorf(fmaxf(blo[i], -4.0f)) - 1;
             hi[i] = (int)__builtin_floorf(fminf(bhi[i], 1.0e7f)) + 1;
         }
-        lo[a] = c0;
-        hi[a] = c1 - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = i == a ? c0 : lo[i];
+            hi[i] = i == a ? c1 - 1 : hi[i];
+        }
         Box b;
         if (!make_box(lo, hi, clo, chi, a, b)) continue;
         __syncthreads();
@@ -322,7 +335,8 @@ struct Bundle {
 };
 
 __global__ void __launch_bounds__(256) k_forward_interp(const float* __restrict__ vol, float* __restrict__ proj,
-                                                        const ViewGeo* __restrict__ tab, int view0, TileMap m,
+                                                        const ViewGeo* __restrict__ tab,
+                                                        const ViewGeo64* __restrict__ tab64, int view0, TileMap m,
                                                         VolDims v, DetDims det, float ds)
 {
     __shared__ float box[BOXCAP];
@@ -350,11 +364,11 @@ __global__ void __launch_bounds__(256) k_forward_interp(const float* __restrict_
     }
 
     InterpRay r;
-    const bool has = interp_ray(g, active ? iu : 0, active ? iv : 0, v, ds, r) && active;
+    const bool has = interp_ray(tab64[view0 + view], active ? iu : 0, active ? iv : 0, v, ds, r) && active;
     int k = has ? r.k0 : 0;
     const int k1 = has ? r.k1 : -1;
-    // sample k sits at base + (k - k0) st; along the dominant axis the slab
-    // boundary plane P is reached at (k - k0) = (P - base_a) / st_a
+    // sample k sits at base + (k - kc) st; along the dominant axis the slab
+    // boundary plane P is reached at (k - kc) = (P - base_a) / st_a
     const float sa = a == 0 ? r.st[0] : (a == 1 ? r.st[1] : r.st[2]);
     const float ba = a == 0 ? r.base[0] : (a == 1 ? r.base[1] : r.base[2]);
     // the slab bookkeeping needs the ray to advance along the tile's direction
@@ -394,14 +408,17 @@ __global__ void __launch_bounds__(256) k_forward_interp(const float* __restrict_
             lo[i] = (int)__builtin_floorf(fmaxf(blo[i], -4.0f)) - 1;
             hi[i] = (int)__builtin_floorf(fminf(bhi[i], 1.0e7f)) + 2;
         }
-        lo[a] = A0 - 1;
-        hi[a] = A1 + 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = i == a ? A0 - 1 : lo[i];
+            hi[i] = i == a ? A1 + 1 : hi[i];
+        }
         // this thread's last sample in the slab
         int kl;
         {
             const float P = dir > 0 ? (float)A1 : (float)A0;
             const float t = (P - ba) * inv_sa;
-            kl = r.k0 + (dir > 0 ? (int)__builtin_ceilf(t) - 1 : (int)__builtin_floorf(t));
+            kl = r.kc + (dir > 0 ? (int)__builtin_ceilf(t) - 1 : (int)__builtin_floorf(t));
             kl = (si == nslab - 1 || !mono) ? k1 : min(kl, k1);
         }
         Box b;
@@ -480,7 +497,7 @@ hipError_t launch_forward_siddon(const Plan& p, const float* vol, float* proj, i
 {
     const TileMap m = tile_map(p, nviews);
     const int64_t blocks = (int64_t)m.tiles_u * m.tiles_v * nviews;
-    hipLaunchKernelGGL(k_forward_siddon, dim3((unsigned)blocks), dim3(256), 0, s, vol, proj, p.d_views,
+    hipLaunchKernelGGL(k_forward_siddon, dim3((unsigned)blocks), dim3(256), 0, s, vol, proj, p.d_views, p.d_views64,
                        (int)view0, m, p.vol, p.det);
     return hipGetLastError();
 }
@@ -490,7 +507,7 @@ hipError_t launch_forward_interp(const Plan& p, const float* vol, float* proj, i
 {
     const TileMap m = tile_map(p, nviews);
     const int64_t blocks = (int64_t)m.tiles_u * m.tiles_v * nviews;
-    hipLaunchKernelGGL(k_forward_interp, dim3((unsigned)blocks), dim3(256), 0, s, vol, proj, p.d_views,
+    hipLaunchKernelGGL(k_forward_interp, dim3((unsigned)blocks), dim3(256), 0, s, vol, proj, p.d_views, p.d_views64,
                        (int)view0, m, p.vol, p.det, p.ds);
     return hipGetLastError();
 }

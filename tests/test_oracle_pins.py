@@ -482,3 +482,30 @@ def test_psnr_closed_form():
     g[1, 1, 1] = 2.0
     x = g + 0.01
     assert abs(oracle.psnr(x, g) - 20 * math.log10(2.0 / 0.01)) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_gradient_voxels_matches_dense_normal_equations(orc, kind):
+    """The per-voxel gradient 2 (A^T (A x - y))_j against 2 M^T (M x - y)
+    with the explicit matrix."""
+    geo = TINY
+    ang = _angles(4, 51)
+    M = orc.dense_matrix(geo, ang, kind)
+    rng = np.random.Generator(np.random.PCG64(52))
+    x = rng.random(geo.nVoxel)
+    y = rng.random((len(ang),) + geo.nDetector)
+    want = 2.0 * M.T @ (M @ x.ravel() - y.ravel())
+    sel = rng.integers(0, geo.n_vox, 40)
+    iz, iy, ix = np.unravel_index(sel, geo.nVoxel)
+    got = orc.gradient_voxels(geo, ang, x, y, iz, iy, ix, kind)
+    assert np.allclose(got, want[sel], rtol=1e-11, atol=1e-11 * np.abs(want).max())
+
+
+def test_bfdk_voxels_equals_full_backprojector(orc):
+    geo = TINY_ANISO
+    ang = _angles(6, 53)
+    q = np.random.Generator(np.random.PCG64(54)).random((6,) + geo.nDetector)
+    full = orc.bfdk(geo, ang, q)
+    sel = np.arange(0, geo.n_vox, 7)
+    iz, iy, ix = np.unravel_index(sel, geo.nVoxel)
+    assert np.array_equal(orc.bfdk_voxels(geo, ang, q, iz, iy, ix), full.ravel()[sel])
