@@ -27,7 +27,8 @@ import numpy as np
 __all__ = [
     "Geometry", "Ellipsoid", "WORKLOADS", "workload", "circular_angles",
     "head_phantom", "random_ellipsoids", "voxelize", "gaussian_texture",
-    "uniform_volume", "uniform_projections", "poisson_log_data",
+    "uniform_volume", "uniform_projections", "poisson_log_data", "normal_weights",
+    "bf16_values",
 ]
 
 
@@ -288,3 +289,18 @@ def poisson_log_data(p: np.ndarray, seed: int, I0: float = 1e5, mu_w: float = 0.
     lam = I0 * np.exp(-mu_w * np.asarray(p, dtype=np.float64))
     N = rng.poisson(lam)
     return (-np.log(np.maximum(N, 1) / I0) / mu_w).astype(np.asarray(p).dtype)
+
+
+def normal_weights(seed: int, specs) -> List[np.ndarray]:
+    """Initial network weights: for each (shape, std) in `specs`, in order,
+    N(0, std^2) values from one seeded PCG64 stream, as FP32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [(rng.standard_normal(tuple(shape)) * std).astype(np.float32) for shape, std in specs]
+
+
+def bf16_values(shape, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Uniform values in [lo, hi) that are exactly representable in BF16
+    (FP32 numbers whose low 16 bits are zero), as FP32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.uniform(lo, hi, tuple(shape)).astype(np.float32)
+    return (a.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
