@@ -255,6 +255,59 @@ def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, 
     return x, hist
 
 
+def pnp_cgls(geo: Geometry, angles, b, niter: int, denoiser, every: int = 5, ratio: float = 1.05,
+             kind: str = "interp", x_gt=None, mask=None):
+    """CGLS with a plug-and-play denoiser (the learned prior used inside the
+    paper's Krylov solvers, section 2.2.1; the combination is this build's).
+
+    Runs CGLS from x = 0.  After every `every` iterations it proposes
+    x' = denoiser(x) and computes r' = b - A x'.  The proposal is accepted
+    when |r'| <= ratio |r|, r the CGLS residual vector; CGLS then restarts
+    at x' (r = r', s = p = A^T r', gamma = |s|^2).  A rejected proposal
+    changes nothing: CGLS continues as if it had not been made, so with a
+    denoiser that is always rejected the iterates are those of `cgls`.
+    Returns (x, hist) with the per-iteration residual norms |r_k|, the
+    proposals' ratios |r'| / |r| and decisions, and the PSNR history when
+    x_gt is given.
+    """
+    b = _f64(b)
+    x = np.zeros(geo.nVoxel)
+    r = b.copy()
+    s = backward(geo, angles, r, kind)
+    p = s.copy()
+    gamma = float(np.dot(s.ravel(), s.ravel()))
+    hist = {"resid": [], "psnr": [], "ratios": [], "accepted": []}
+    for k in range(niter):
+        if gamma > 0.0:
+            q = forward(geo, angles, p, kind)
+            delta = float(np.dot(q.ravel(), q.ravel()))
+            alpha = gamma / delta if delta > 0.0 else 0.0
+            x = x + alpha * p
+            r = r - alpha * q
+            s = backward(geo, angles, r, kind)
+            gamma_new = float(np.dot(s.ravel(), s.ravel()))
+            beta = gamma_new / gamma
+            p = s + beta * p
+            gamma = gamma_new
+        if (k + 1) % every == 0:
+            xd = _f64(denoiser(x))
+            rd = b - forward(geo, angles, xd, kind)
+            nr = float(np.linalg.norm(r.ravel()))
+            q_ = float(np.linalg.norm(rd.ravel())) / nr if nr > 0.0 else math.inf
+            hist["ratios"].append(q_)
+            acc = q_ <= ratio
+            hist["accepted"].append(bool(acc))
+            if acc:
+                x, r = xd, rd
+                s = backward(geo, angles, r, kind)
+                p = s.copy()
+                gamma = float(np.dot(s.ravel(), s.ravel()))
+        hist["resid"].append(float(np.linalg.norm(r.ravel())))
+        if x_gt is not None:
+            hist["psnr"].append(psnr(x, x_gt, mask))
+    return x, hist
+
+
 def subsets(nviews: int, blocksize: int):
     """Consecutive view blocks visited in order (the paper's ordered
     subsets, section 2.2.2, sequential ordering)."""

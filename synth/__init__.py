@@ -28,7 +28,7 @@ __all__ = [
     "Geometry", "Ellipsoid", "WORKLOADS", "workload", "circular_angles",
     "head_phantom", "random_ellipsoids", "voxelize", "gaussian_texture",
     "uniform_volume", "uniform_projections", "poisson_log_data", "normal_weights",
-    "bf16_values",
+    "bf16_values", "textured_phantom",
 ]
 
 
@@ -304,3 +304,12 @@ def bf16_values(shape, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarr
     rng = np.random.Generator(np.random.PCG64(seed))
     a = rng.uniform(lo, hi, tuple(shape)).astype(np.float32)
     return (a.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+
+
+def textured_phantom(geo: Geometry, seed: int, dtype=np.float32) -> np.ndarray:
+    """Random-ellipsoid phantom plus a smooth texture on its support
+    (Gaussian-filtered white noise, sigma 4 voxels, std 0.02), clamped at 0.
+    Ellipsoids from `seed`, texture noise from seed + 1_000_000."""
+    v = voxelize(geo, random_ellipsoids(geo, seed), dtype=np.float64)
+    v = v + gaussian_texture(geo, seed + 1_000_000, v > 0)
+    return np.maximum(v, 0.0).astype(dtype)

@@ -509,3 +509,57 @@ def test_bfdk_voxels_equals_full_backprojector(orc):
     sel = np.arange(0, geo.n_vox, 7)
     iz, iy, ix = np.unravel_index(sel, geo.nVoxel)
     assert np.array_equal(orc.bfdk_voxels(geo, ang, q, iz, iy, ix), full.ravel()[sel])
+
+
+# ------------------------------------------------------------ PnP-CGLS
+def _pnp_setup():
+    from synth import Geometry
+    geo = Geometry(DSD=400.0, DSO=250.0, nVoxel=(16, 16, 16), dVoxel=(1.0, 1.0, 1.0), nDetector=(24, 24),
+                   dDetector=(1.5, 1.5))
+    ang = synth.circular_angles(12)
+    x_gt = synth.voxelize(geo, synth.random_ellipsoids(geo, 5), dtype=np.float64)
+    return geo, ang, x_gt
+
+
+def test_pnp_cgls_rejected_denoiser_is_plain_cgls(orc):
+    geo, ang, x_gt = _pnp_setup()
+    b = orc.forward(geo, ang, x_gt, "interp")
+    x0, h0 = orc.cgls(geo, ang, b, 12, kind="interp")
+    bad = lambda x: x + 100.0                      # residual explodes: always rejected
+    x1, h1 = orc.pnp_cgls(geo, ang, b, 12, bad, every=4, kind="interp")
+    assert h1["accepted"] == [False, False, False] and min(h1["ratios"]) > 10
+    assert np.array_equal(x0, x1)
+    assert np.allclose(h1["resid"], h0["resid"], rtol=0, atol=0)
+
+
+def test_pnp_cgls_exact_denoiser_reaches_ground_truth(orc):
+    """b = A x_gt exactly; a denoiser returning x_gt has residual 0, is
+    accepted, and the restarted CGLS stays there (gamma = 0)."""
+    geo, ang, x_gt = _pnp_setup()
+    b = orc.forward(geo, ang, x_gt, "siddon")
+    x, h = orc.pnp_cgls(geo, ang, b, 10, lambda x: x_gt, every=5, kind="siddon", x_gt=x_gt)
+    assert h["accepted"][0] and h["ratios"][0] < 1e-12
+    assert np.array_equal(x, x_gt) and h["psnr"][-1] == np.inf
+    assert h["resid"][4] < 1e-9 and h["resid"][-1] < 1e-9
+
+
+def test_pnp_cgls_identity_denoiser_restarts_cgls(orc):
+    """The identity is always accepted (ratio 1 up to the recurrence's
+    drift) and restarts CGLS, which is then CGLS started from x_5."""
+    geo, ang, x_gt = _pnp_setup()
+    b = orc.forward(geo, ang, x_gt, "interp")
+    x, h = orc.pnp_cgls(geo, ang, b, 9, lambda x: x, every=5, kind="interp")
+    assert h["accepted"] == [True] and abs(h["ratios"][0] - 1.0) < 1e-9
+    x5, _ = orc.cgls(geo, ang, b, 5, kind="interp")
+    # four more CGLS steps from x5 with r = b - A x5
+    r = b - orc.forward(geo, ang, x5, "interp")
+    s = orc.backward(geo, ang, r, "interp")
+    p, gam, xx = s.copy(), float(np.vdot(s, s)), x5.copy()
+    for _ in range(4):
+        q = orc.forward(geo, ang, p, "interp")
+        al = gam / float(np.vdot(q, q))
+        xx, r = xx + al * p, r - al * q
+        s = orc.backward(geo, ang, r, "interp")
+        g2 = float(np.vdot(s, s))
+        p, gam = s + (g2 / gam) * p, g2
+    assert np.max(np.abs(x - xx)) < 1e-10 * np.max(np.abs(xx))
