@@ -42,6 +42,69 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 #     fraction 1, 1 - f 1, two u-lerps 6, v-lerp 3, weight fma 2       = 16
 FLOPS = {"interp_fwd": 37, "interp_bwd": 47, "siddon_fwd": 10, "siddon_bwd": 11, "fdk_bp": 16}
 
+# source file of each timed kernel (the HBM traffic recorded for a kernel in
+# profiles/traffic.json is used only while that file is unchanged)
+KERNEL_SOURCE = {"interp_fwd": "forward.hip", "siddon_fwd": "forward.hip", "interp_bwd": "backward.hip",
+                 "siddon_bwd": "backward.hip", "fdk_bp": "fdk.hip"}
+
+
+def _sha256(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs recorded in profiles/traffic.json, scaled by the plain-copy
+    calibration stored there; None if absent or if the kernel's source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    src = os.path.join(ROOT, "paper_2412_10129_amd", "csrc", KERNEL_SOURCE[kernel])
+    if not k or not os.path.exists(src) or k.get("source_sha256") != _sha256(src):
+        return None
+    cal = rec["calibration"]
+    return int(1024 * (k["fetch_kib"] * cal["fetch_factor"] + k["write_kib"] * cal["write_factor"]))
+
+
+def profile_summary(db_path, top=12):
+    """Markdown tables of a rocprofv3 results database: kernel durations
+    (kernel trace) and per-dispatch averages of any PMC counters."""
+    import collections
+    import re
+    import sqlite3
+    con = sqlite3.connect(db_path)
+    short = lambda n: re.split(r"[(<]", n.replace("ctmi::(anonymous namespace)::", ""))[0].strip()
+    lines = []
+    tables = {r[0] for r in con.execute("select name from sqlite_master where type in ('table', 'view')")}
+    if "top_kernels" in tables:
+        rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+        if rows:
+            lines += ["| kernel | calls | avg (ms) | total (ms) | % |", "|---|---|---|---|---|"]
+            for name, calls, tot, avg, pct in rows[:top]:
+                lines.append(f"| {short(name)} | {calls} | {avg / 1e3:.3f} | {tot / 1e3:.3f} | {pct:.2f} |")
+    if "pmc_events" in tables:
+        rows = con.execute("select name, dispatch_id, counter_name, sum(counter_value) from pmc_events "
+                           "group by name, dispatch_id, counter_name").fetchall()
+        acc = collections.defaultdict(lambda: collections.defaultdict(list))
+        for name, _, cn, v in rows:
+            acc[short(name)][cn].append(v)
+        if acc:
+            cnames = sorted({c for d in acc.values() for c in d})
+            lines += ["", "| kernel | dispatches | " + " | ".join(f"{c} (avg/dispatch)" for c in cnames) + " |",
+                      "|---|---|" + "---|" * len(cnames)]
+            for k, d in sorted(acc.items()):
+                nd = max(len(v) for v in d.values())
+                vals = " | ".join(f"{sum(d[c]) / len(d[c]):.6g}" if c in d else "" for c in cnames)
+                lines.append(f"| {k} | {nd} | {vals} |")
+    return "\n".join(lines)
+
 
 def _rays(geo, angles):
     """Ray end points in voxel-cell coordinates for the listed views (FP64)."""
@@ -125,7 +188,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--profile-summary", metavar="DB",
+                    help="only print markdown tables of a rocprofv3 results database and exit")
     args = ap.parse_args()
+    if args.profile_summary:
+        print(profile_summary(args.profile_summary))
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -230,7 +298,8 @@ def main():
     fl = FLOPS[dominant] * units[dominant]
     ach = fl / (t_dom / 1e3) / 1e12
     roofline = {"bound": "alu", "kernel": dominant, "achieved": round(ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                "traffic": recorded_traffic(dominant),
                 "work_units": units[dominant], "flops_per_unit": FLOPS[dominant],
                 "avg_launch_ms": round(float(t_dom), 3)}
 
