@@ -62,6 +62,28 @@ _SIGS = {
     "ctmi_sart_residual": (c_int, [c_p, c_p, c_p, c_p, c_i64, c_p]),
     "ctmi_sart_update": (c_int, [c_p, c_p, c_p, c_i64, c_f, c_int, c_p]),
     "ctmi_fov_sq_err": (c_int, [c_p, c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
+    # learned prior (ctmi_unet.h)
+    "ctmi_conv3d_bf16_fwd": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_int, c_p, c_p, c_int, c_int, c_p,
+                                                   c_int, c_p]),
+    "ctmi_conv3d_bf16_dgrad": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_p, c_int, c_p, c_int, c_p]),
+    "ctmi_conv3d_wgrad_workspace_bytes": (ctypes.c_size_t, [c_int] * 6),
+    "ctmi_conv3d_bf16_wgrad": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_int, c_p, c_int, c_int, c_p, c_p,
+                                                     c_int, c_p, ctypes.c_size_t, c_p]),
+    "ctmi_conv3d_pack_weights": (c_int, [c_p, c_int, c_int, c_p, c_p, c_p]),
+    "ctmi_unet_pack_input": (c_int, [c_p, c_i64, c_p, c_p]),
+    "ctmi_pool2": (c_int, [c_int] * 5 + [c_p, c_int, c_p, c_int, c_p]),
+    "ctmi_pool2_skip_grad": (c_int, [c_int] * 5 + [c_p, c_int, c_p, c_int, c_p, c_int, c_p, c_int, c_p]),
+    "ctmi_upsample2": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_p, c_int, c_p, c_int, c_p]),
+    "ctmi_upsample2_dgrad": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_p, c_int, c_p, c_int, c_p]),
+    "ctmi_upsample2_wgrad_workspace_bytes": (ctypes.c_size_t, [c_int] * 6),
+    "ctmi_upsample2_wgrad": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_int, c_p, c_p, c_int, c_p,
+                                                   ctypes.c_size_t, c_p]),
+    "ctmi_unet_head": (c_int, [c_i64, c_p, c_p, c_int, c_int, c_p, c_p, c_p, c_p]),
+    "ctmi_unet_head_workspace_bytes": (ctypes.c_size_t, []),
+    "ctmi_unet_head_mse_bwd": (c_int, [c_i64, c_p, c_p, c_p, c_int, c_p, c_p, c_int, c_p, c_p, c_p, ctypes.c_size_t,
+                                       c_p]),
+    "ctmi_adam_step": (c_int, [c_p, c_p, c_p, c_p, c_i64, c_f, c_f, c_f, c_f, c_i64, c_p]),
+    "ctmi_to_bf16": (c_int, [c_p, c_i64, c_p, c_p]),
 }
 
 EXPORTED = tuple(_SIGS)

@@ -6,6 +6,7 @@ a loop never waits for the host.
 """
 from __future__ import annotations
 
+import ctypes
 import math
 from typing import Optional
 
@@ -28,7 +29,7 @@ def _addr(t: torch.Tensor, i: int, j: int) -> int:
 
 
 def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Optional[torch.Tensor] = None,
-         x0: Optional[torch.Tensor] = None, sync: bool = True):
+         x0: Optional[torch.Tensor] = None, sync: bool = True, snapshots=()):
     """CGLS (Hestenes-Stiefel; the Krylov solvers of section 2.2.1).
 
     x0 = 0 (or the given start); r = b - A x0; s = A^T r; p = s; gamma = |s|^2;
@@ -38,7 +39,8 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
     Returns (x, hist): hist holds per-iteration gamma, delta, |r|^2 and, given
     x_gt, the squared error and voxel count inside the FOV (the residual and
     error-norm histories of section 2.2.3).  With sync=False, hist holds the
-    device tensors instead of host arrays.
+    device tensors instead of host arrays.  hist["snapshots"][k] is a copy of
+    the iterate after k iterations for every k in `snapshots`.
     """
     dev = plan.device
     vol_shape, proj_shape = plan.vol_shape, plan.proj_shape()
@@ -55,6 +57,7 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
     s = plan.backproject(r, kind=kind)
     p = s.clone()
     q = torch.empty(proj_shape, dtype=torch.float32, device=dev)
+    snaps = {int(k): None for k in snapshots}
     ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(s, "s"), ops._ptr(s, "s"), s.numel(), _addr(sc, 0, 0),
                                      ws.data_ptr(), ws.numel() * 8, ops._stream()))
     for k in range(niter):
@@ -68,12 +71,14 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
         ops.cgls_p(p, s, _addr(sc, k, 0), _addr(sc, k + 1, 0))
         if x_gt is not None:
             plan.fov_sq_err(x, x_gt, err[k])
-    hist = {"scalars": sc, "err": err}
+        if k + 1 in snaps:
+            snaps[k + 1] = x.clone()
+    hist = {"scalars": sc, "err": err, "snapshots": snaps}
     if sync:
         h = sc.cpu().numpy()
         hist = {"gamma": h[:, 0], "delta": h[:niter, 1], "resid": np.sqrt(h[:niter, 2]),
                 "alpha": h[:niter, 0] / np.where(h[:niter, 1] != 0, h[:niter, 1], np.inf),
-                "beta": h[1:, 0] / np.where(h[:niter, 0] != 0, h[:niter, 0], np.inf)}
+                "beta": h[1:, 0] / np.where(h[:niter, 0] != 0, h[:niter, 0], np.inf), "snapshots": snaps}
         stop = np.nonzero((h[:niter, 1] == 0) | (h[:niter, 0] == 0))[0]
         hist["stopped"] = int(stop[0]) if len(stop) else None
         if x_gt is not None:
@@ -136,3 +141,93 @@ class OSSART:
 def os_sart(plan: Plan, b: torch.Tensor, niter: int, blocksize: int, lam: float = 1.0, nonneg: bool = True,
             kind: str = "interp", x0: Optional[torch.Tensor] = None) -> torch.Tensor:
     return OSSART(plan, blocksize, kind).run(b, niter, lam, nonneg, x0)
+
+
+def pnp_cgls(plan: Plan, b: torch.Tensor, niter: int, denoiser, every: int = 5, ratio: float = 1.05,
+             kind: str = "interp", x_gt: Optional[torch.Tensor] = None, data_range: Optional[float] = None,
+             timing: bool = False):
+    """CGLS with a plug-and-play denoiser step (the learned prior inside the
+    Krylov solver of section 2.2.1).
+
+    CGLS from x = 0; after every `every` iterations, x' = denoiser(x) and
+    r' = b - A x'; when |r'| <= ratio |r| (r the CGLS residual vector) CGLS
+    restarts at x' (r = r', s = p = A^T r', gamma = |s|^2), otherwise the
+    proposal is dropped and CGLS continues unchanged.  One host
+    synchronisation per proposal takes the decision.
+
+    Returns (x, hist): per-iteration residual norms, the proposals' ratios and
+    decisions, with x_gt the FOV squared errors (and PSNR given data_range),
+    and with timing=True the per-iteration solver time in ms (GPU events
+    around each iteration's kernels, error bookkeeping excluded).
+    """
+    dev = plan.device
+    ws = ops._ws(dev)
+    npro = niter // every
+    g = torch.zeros(niter + npro + 2, dtype=torch.float64, device=dev)     # gamma slots
+    sc = torch.zeros((niter, 3), dtype=torch.float64, device=dev)          # delta_k, |r_k|^2, |r'|^2
+    err = torch.zeros((niter, 2), dtype=torch.float64, device=dev)
+    x = torch.zeros(plan.vol_shape, dtype=torch.float32, device=dev)
+    r = b.clone()
+    s = plan.backproject(r, kind=kind)
+    p = s.clone()
+    q = torch.empty(plan.proj_shape(), dtype=torch.float32, device=dev)
+    rd = torch.empty_like(q)
+    lib, st = ops.L.lib(), ops._stream()
+
+    def dot_into(a, addr):
+        ops.L.check(lib.ctmi_dot(ops._ptr(a, "a"), ops._ptr(a, "a"), a.numel(), ctypes.c_void_p(addr),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel() * 8, st))
+
+    gaddr = lambda i: g.data_ptr() + 8 * i
+    dot_into(s, gaddr(0))
+    gi = 0
+    ratios, accepted, resid_from_proposal = [], [], {}
+    ev = []
+    for k in range(niter):
+        if timing:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+        plan.forward(p, out=q, kind=kind)
+        dot_into(q, _addr(sc, k, 0))
+        ops.cgls_xr(x, p, r, q, gaddr(gi), _addr(sc, k, 0), _addr(sc, k, 1), ws)
+        plan.backproject(r, out=s, kind=kind)
+        dot_into(s, gaddr(gi + 1))
+        ops.cgls_p(p, s, gaddr(gi), gaddr(gi + 1))
+        gi += 1
+        if (k + 1) % every == 0:
+            xd = denoiser(x)
+            plan.forward(xd, out=rd, kind=kind)
+            ops.axpby(1.0, b, -1.0, rd)
+            dot_into(rd, _addr(sc, k, 2))
+            h = sc[k].cpu().numpy()
+            qk = math.sqrt(h[2] / h[1]) if h[1] > 0 else math.inf
+            ratios.append(qk)
+            accepted.append(bool(qk <= ratio))
+            if accepted[-1]:
+                x.copy_(xd)
+                r.copy_(rd)
+                plan.backproject(r, out=s, kind=kind)
+                p.copy_(s)
+                dot_into(s, gaddr(gi + 1))
+                gi += 1
+                resid_from_proposal[k] = math.sqrt(h[2])
+        if timing:
+            e1 = torch.cuda.Event(enable_timing=True)
+            e1.record()
+            ev.append((e0, e1))
+        if x_gt is not None:
+            plan.fov_sq_err(x, x_gt, err[k])
+    h = sc.cpu().numpy()
+    resid = np.sqrt(h[:, 1])
+    for k, v in resid_from_proposal.items():
+        resid[k] = v
+    hist = {"resid": resid, "ratios": ratios, "accepted": accepted}
+    if x_gt is not None:
+        e = err.cpu().numpy()
+        hist["sq_err"], hist["count"] = e[:, 0], e[:, 1]
+        if data_range is not None:
+            hist["psnr"] = psnr_from_sq_err(e[:, 0], e[:, 1], data_range)
+    if timing:
+        torch.cuda.synchronize()
+        hist["ms"] = np.array([a.elapsed_time(bb) for a, bb in ev])
+    return x, hist

@@ -25,6 +25,8 @@
 // Integer addition is associative, so the result is bit-reproducible.
 #include "ctmi_internal.h"
 
+#include <type_traits>
+
 namespace ctmi {
 
 namespace {
@@ -42,6 +44,7 @@ constexpr int BX = 16, BY = 16, BZ = CTMI_BWD_BZ;   // brick (voxels)
 constexpr int NB = BX * BY * BZ;
 constexpr int OWN = NB / 256;                     // voxels owned per thread
 typedef unsigned long long u64;
+typedef long long i64;
 
 struct BrickMap {
     int nbx, nby, nbz;
@@ -112,6 +115,17 @@ __device__ __forceinline__ int block_scan(int v, int* wsum, int* total)
     return off + x - v;
 }
 
+// Item -> ray map of one round: ray r owns items [pre[r], pre[r] + cnt).  The
+// first MAPCAP items are looked up in a byte table written by the rays
+// themselves; later ones (rare) by binary search over pre.
+constexpr int MAPCAP = 4096;
+
+__device__ __forceinline__ void fill_item_map(unsigned char* map, int off, int cnt)
+{
+    const int e = min(off + cnt, MAPCAP);
+    for (int i = off; i < e; ++i) map[i] = (unsigned char)threadIdx.x;
+}
+
 // Largest r in [0, 255] with pre[r] <= it (pre non-decreasing).
 __device__ __forceinline__ int owner(const int* pre, int it)
 {
@@ -126,25 +140,26 @@ __device__ __forceinline__ int owner(const int* pre, int it)
 }
 
 // Fixed-point scale for one (brick, group of views): the largest power of
-// two s with s * cmax * maxy <= 2^31, cmax a bound on a single matrix entry,
-// so every contribution a_ij y_i fits an int32 with 2^-31 of the largest
-// one as resolution.  Returns s and writes 1/s.
+// two s with s * cmax * maxy <= 2^30, cmax a bound on a single contribution's
+// matrix factor (one Siddon chord, or one interpolation sample's ds), so
+// every contribution a y_i fits an int32 with 2^-30 of the largest one as
+// resolution.  Returns s and writes 1/s.
 __device__ __forceinline__ float fixed_scale(float cmax, float maxy, float* inv)
 {
     int e;
-    (void)__builtin_frexpf(0x1p31f / (cmax * maxy), &e);
+    (void)__builtin_frexpf(0x1p30f / (cmax * maxy), &e);
     e = min(max(e - 1, -120), 120);
     *inv = __builtin_ldexpf(1.0f, -e);
     return __builtin_ldexpf(1.0f, e);
 }
 
-// A contribution q (|q| <= 2^31, already scaled) as a sign-extended 64-bit
-// two's-complement integer (truncated toward zero: a bias below one unit).
-// The 64-bit accumulators then hold the exact sum of up to 2^32 such terms.
+// A contribution q (|q| <= 2^30 by the choice of scale) as a sign-extended
+// 64-bit two's-complement integer (truncated toward zero: a bias below one
+// unit).  The 64-bit accumulators then hold the exact sum of up to 2^33
+// such terms.
 __device__ __forceinline__ u64 to_fixed(float q)
 {
-    const int v = (int)fminf(fmaxf(q, -2147483520.0f), 2147483520.0f);
-    return (u64)(long long)v;
+    return (u64)(long long)(int)q;
 }
 
 // Views are processed in groups of GV: one fixed-point scale (from the max
@@ -217,17 +232,18 @@ __device__ __forceinline__ float group_max(GroupLds& G, const float* __restrict_
 // Add the view's fixed-point sums into the owned FP32 registers and clear
 // the integer accumulator (voxel (lx, ly, lz) of the brick sits at
 // ((lz + pad) * py + ly + pad) * px + lx + pad).
-__device__ __forceinline__ void flush_view(u64* acc, int n_acc, int px, int py, int pad, float inv, float own[OWN])
+template <typename Acc>
+__device__ __forceinline__ void flush_view(Acc* acc, int n_acc, int px, int py, int pad, float inv, float own[OWN])
 {
 #pragma unroll
     for (int m = 0; m < OWN; ++m) {
         const int i = threadIdx.x + 256 * m;
         const int lx = i % BX, ly = (i / BX) % BY, lz = i / (BX * BY);
-        const long long a = (long long)acc[((lz + pad) * py + (ly + pad)) * px + (lx + pad)];
-        own[m] = __builtin_fmaf((float)a, inv, own[m]);
+        const Acc a = acc[((lz + pad) * py + (ly + pad)) * px + (lx + pad)];
+        own[m] = __builtin_fmaf((float)(long long)a, inv, own[m]);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0;
 }
 
 __device__ __forceinline__ void store_owned(float* __restrict__ vol, const float own[OWN], const VolDims& v, int x0,
@@ -254,6 +270,7 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
     __shared__ float t_S[3][256], t_d[3][256];
     __shared__ float t_a0[256], t_a1[256], t_y[256];
     __shared__ int t_c0[256], t_nc[256], t_pre[256];
+    __shared__ unsigned char imap[MAPCAP];
     __shared__ int wsum[4];
     __shared__ GroupLds G;
     for (int i = threadIdx.x; i < NB; i += blockDim.x) acc[i] = 0ull;
@@ -324,8 +341,12 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
             const int off = block_scan(cnt, wsum, &total);
             t_pre[tid] = off;
             __syncthreads();
+            fill_item_map(imap, off, cnt);
+            __syncthreads();
+            // items are taken round-robin (consecutive lanes on consecutive
+            // items keep every lane's trip count at most SID_CELLS cells)
             for (int it = tid; it < total; it += 256) {
-                const int r = owner(t_pre, it);
+                const int r = it < MAPCAP ? (int)imap[it] : owner(t_pre, it);
                 const int q = it - t_pre[r];
                 const float S[3] = {t_S[0][r], t_S[1][r], t_S[2][r]};
                 const float d[3] = {t_d[0][r], t_d[1][r], t_d[2][r]};
@@ -357,6 +378,7 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
                 const int sx = ax.step, sy = ay.step * BX, sz = az.step * BX * BY;
                 const float yl = t_y[r];
                 float acur = astart;
+                asm volatile("" ::"v"(yl), "v"(acur), "v"(aend), "v"(li));
                 for (int step = 0; step < BX + BY + BZ + 3; ++step) {
                     const float an = fminf(anx, fminf(any, anz));
                     const float ae = fminf(an, aend);
@@ -395,6 +417,28 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;   // interpolated accumulator: brick plus a one-voxel halo
 constexpr int INT_SAMPLES = CTMI_BWD_INT_SAMPLES;  // samples per interpolated item
 
+// Accumulator cells of the interpolated adjoint.  64-bit: each contribution
+// is an int32 against the per-(brick, group) scale and the cells hold the
+// group's exact sums.  32-bit (ACC32): the scale also covers every term one
+// round of 256 rays can add to one cell (the plan's factor 256 K, K the most
+// samples of one ray inside a 2x2x2-voxel support), the cells are flushed
+// after every round, and contributions are rounded to nearest; 32-bit LDS
+// atomics run about 1.4x faster than 64-bit ones.
+#ifndef CTMI_BWD_ACC32
+#define CTMI_BWD_ACC32 0
+#endif
+constexpr bool ACC32 = CTMI_BWD_ACC32 != 0;
+typedef std::conditional<ACC32, int, u64>::type IAcc;
+
+__device__ __forceinline__ void iacc_add(IAcc* a, float q)
+{
+    if constexpr (ACC32) {
+        atomicAdd(a, (int)__builtin_rintf(q));
+    } else {
+        atomicAdd(a, to_fixed(q));
+    }
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
                                                          const ViewGeo64* __restrict__ tab64, int view0, int nviews,
@@ -404,12 +448,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     // accumulator over voxels [b0 - 1, b1] per axis; the halo takes the
     // corners that fall outside the brick and is discarded, so every sample
     // scatters to 8 fixed offsets without per-corner tests
-    __shared__ u64 acc[HX * HY * HZ];
-    __shared__ float t_base[3][256], t_st[3][256], t_y[256];
-    __shared__ int t_j[256], t_n[256], t_pre[256];
+    __shared__ IAcc acc[HX * HY * HZ];
+    // ray table: (base, y) and (st, first sample | sample count << 16)
+    __shared__ float4 t_a[256], t_b[256];
+    __shared__ int t_pre[256];
+    __shared__ unsigned char imap[MAPCAP];
     __shared__ int wsum[4];
     __shared__ GroupLds G;
-    for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0;
     float own[OWN];
 #pragma unroll
     for (int i = 0; i < OWN; ++i) own[i] = 0.0f;
@@ -421,8 +467,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     // voxel-centre coordinates
     const float lo[3] = {x0 - 1.0f, y0 - 1.0f, z0 - 1.0f};
     const float hi[3] = {(float)x1, (float)y1, (float)z1};
-    const int hx = x1 - x0, hy = y1 - y0, hz = z1 - z0;   // valid halo-local corner index range [0, h]
+    // a sample's lower corner (floor of its position) must lie in
+    // [lo, hi - 1] per axis; the accumulator's byte offset of corner c is
+    // 8 ((c_z - lo_z) HX HY + (c_y - lo_y) HX + (c_x - lo_x)), formed in FP32
+    // (integers below 2^24)
+    const float cmx = hi[0] - 1.0f, cmy = hi[1] - 1.0f, cmz = hi[2] - 1.0f;
+    constexpr float AB = (float)sizeof(IAcc);   // accumulator bytes per cell
+    const float aoff = -AB * (lo[2] * (float)(HX * HY) + lo[1] * (float)HX + lo[0]);
     const int tid = threadIdx.x;
+    char* const accb = reinterpret_cast<char*>(acc);
 
     for (int k = 0; k < nviews; k += GV) {
         const int ng = min(GV, nviews - k);
@@ -442,13 +495,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const float* pk = proj + (int64_t)(k + gv) * det.nv * det.nu;
                 InterpRay ray;
                 if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, ray)) {
-                    // samples (relative to the anchor kc) inside the brick's box
+                    // samples (relative to the anchor kc) inside the brick's box,
+                    // widened by 1e-3 of a sample against the reciprocal's
+                    // rounding (a sample outside the box adds nothing: its
+                    // weights are zeroed below)
                     float kmin = -CTMI_INF, kmax = CTMI_INF;
                     bool inside = true;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         if (ray.st[a] != 0.0f) {
-                            const float ia = 1.0f / ray.st[a];
+                            const float ia = __builtin_amdgcn_rcpf(ray.st[a]);
                             const float ka = (lo[a] - ray.base[a]) * ia, kb = (hi[a] - ray.base[a]) * ia;
                             kmin = fmaxf(kmin, fminf(ka, kb));
                             kmax = fminf(kmax, fmaxf(ka, kb));
@@ -456,20 +512,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                             inside &= ray.base[a] > lo[a] && ray.base[a] < hi[a];
                         }
                     }
-                    if (inside && kmin < kmax) {
-                        const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin));
-                        const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax));
-                        if (ke >= ks) {
-                            const int n = ke - ks + 1;
+                    if (inside && kmin < kmax + 2e-3f) {
+                        const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin - 1e-3f));
+                        const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax + 1e-3f));
+                        const int n = ke - ks + 1;
+                        if (n > 0 && n < 65536) {
                             cnt = (n + INT_SAMPLES - 1) / INT_SAMPLES;
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                t_base[a][tid] = ray.base[a];
-                                t_st[a][tid] = ray.st[a];
-                            }
-                            t_j[tid] = ks - ray.kc;
-                            t_n[tid] = n;
-                            t_y[tid] = pk[(int64_t)iv * det.nu + iu] * ds * scale;
+                            // first sample relative to the anchor: |ks - kc| < 2^15
+                            // because a ray has fewer than 2^15 samples in the
+                            // volume (checked at plan creation)
+                            const int jn = ((ks - ray.kc) & 0xFFFF) | (n << 16);
+                            t_a[tid] = make_float4(ray.base[0], ray.base[1], ray.base[2],
+                                                   pk[(int64_t)iv * det.nu + iu] * ds * scale);
+                            t_b[tid] = make_float4(ray.st[0], ray.st[1], ray.st[2], __int_as_float(jn));
                         }
                     }
                 }
@@ -478,14 +533,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             const int off = block_scan(cnt, wsum, &total);
             t_pre[tid] = off;
             __syncthreads();
+            fill_item_map(imap, off, cnt);
+            __syncthreads();
+            // items are taken round-robin: every lane runs at most
+            // INT_SAMPLES samples per item, so the wave stays converged
             for (int it = tid; it < total; it += 256) {
-                const int r = owner(t_pre, it);
+                const int r = it < MAPCAP ? (int)imap[it] : owner(t_pre, it);
                 const int q = it - t_pre[r];
-                const int j0 = t_j[r] + q * INT_SAMPLES;
-                const int cntq = min(INT_SAMPLES, t_n[r] - q * INT_SAMPLES);
-                const float bxr = t_base[0][r], byr = t_base[1][r], bzr = t_base[2][r];
-                const float sxr = t_st[0][r], syr = t_st[1][r], szr = t_st[2][r];
-                const float yv = t_y[r];
+                const float4 ta = t_a[r], tb = t_b[r];
+                const int jn = __float_as_int(tb.w);
+                const int j0 = (int)(int16_t)(uint16_t)(jn & 0xFFFF) + q * INT_SAMPLES;  // first sample
+                const int cntq = min(INT_SAMPLES, (int)((unsigned)jn >> 16) - q * INT_SAMPLES);
+                const float bxr = ta.x, byr = ta.y, bzr = ta.z, yv = ta.w;
+                const float sxr = tb.x, syr = tb.y, szr = tb.z;
+                // the ray's values must be in registers before the sample
+                // loop, so that the loop never waits on its own atomics
+                asm volatile("" ::"v"(bxr), "v"(byr), "v"(bzr), "v"(sxr), "v"(syr), "v"(szr), "v"(yv), "v"(j0),
+                             "v"(cntq));
                 for (int qq = 0; qq < cntq; ++qq) {
                     // same FP32 position as the forward kernel's sample k
                     const float j = (float)(j0 + qq);
@@ -493,34 +557,43 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     const float py = __builtin_fmaf(j, syr, byr);
                     const float pz = __builtin_fmaf(j, szr, bzr);
                     const float fx = __builtin_floorf(px), fy = __builtin_floorf(py), fz = __builtin_floorf(pz);
-                    // halo-local index of the lower corner, in [0, h] for samples in the box
-                    int lx = (int)fx - (x0 - 1), ly = (int)fy - (y0 - 1), lz = (int)fz - (z0 - 1);
-                    const bool ok = (unsigned)lx <= (unsigned)hx && (unsigned)ly <= (unsigned)hy &&
-                                    (unsigned)lz <= (unsigned)hz;
-                    lx = min(max(lx, 0), hx);
-                    ly = min(max(ly, 0), hy);
-                    lz = min(max(lz, 0), hz);
+                    // corner clamped into the accumulator; a sample whose
+                    // corner moved lies outside the box and adds 0
+                    const float cx = __builtin_amdgcn_fmed3f(fx, lo[0], cmx);
+                    const float cy = __builtin_amdgcn_fmed3f(fy, lo[1], cmy);
+                    const float cz = __builtin_amdgcn_fmed3f(fz, lo[2], cmz);
+                    const bool ok = cx == fx && cy == fy && cz == fz;
+                    const int boff = (int)__builtin_fmaf(cz, AB * (float)(HX * HY),
+                                                         __builtin_fmaf(cy, AB * (float)HX,
+                                                                        __builtin_fmaf(cx, AB, aoff)));
                     const float ax_ = px - fx, ay_ = py - fy, az_ = pz - fz;
                     const float yz1 = ok ? az_ * yv : 0.0f;
                     const float yz0 = ok ? (1.0f - az_) * yv : 0.0f;
                     const float w00 = (1.0f - ay_) * yz0, w10 = ay_ * yz0;
                     const float w01 = (1.0f - ay_) * yz1, w11 = ay_ * yz1;
                     const float bx0 = 1.0f - ax_;
-                    u64* a0 = acc + __umul24(__umul24(lz, HY) + ly, HX) + lx;
-                    atomicAdd(a0, to_fixed(bx0 * w00));
-                    atomicAdd(a0 + 1, to_fixed(ax_ * w00));
-                    atomicAdd(a0 + HX, to_fixed(bx0 * w10));
-                    atomicAdd(a0 + HX + 1, to_fixed(ax_ * w10));
-                    atomicAdd(a0 + HX * HY, to_fixed(bx0 * w01));
-                    atomicAdd(a0 + HX * HY + 1, to_fixed(ax_ * w01));
-                    atomicAdd(a0 + HX * HY + HX, to_fixed(bx0 * w11));
-                    atomicAdd(a0 + HX * HY + HX + 1, to_fixed(ax_ * w11));
+                    IAcc* a0 = reinterpret_cast<IAcc*>(accb + boff);
+                    iacc_add(a0, bx0 * w00);
+                    iacc_add(a0 + 1, ax_ * w00);
+                    iacc_add(a0 + HX, bx0 * w10);
+                    iacc_add(a0 + HX + 1, ax_ * w10);
+                    iacc_add(a0 + HX * HY, bx0 * w01);
+                    iacc_add(a0 + HX * HY + 1, ax_ * w01);
+                    iacc_add(a0 + HX * HY + HX, bx0 * w11);
+                    iacc_add(a0 + HX * HY + HX + 1, ax_ * w11);
                 }
             }
             __syncthreads();
+            if (ACC32) {
+                // 32-bit cells hold one round's sums (bounded by the scale)
+                flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
+                __syncthreads();
+            }
         }
-        flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
-        __syncthreads();
+        if (!ACC32) {
+            flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
+            __syncthreads();
+        }
     }
     store_owned(vol, own, v, x0, y0, z0, beta);
 }
@@ -552,7 +625,7 @@ hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, 
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.entry_interp);
+                       (int)nviews, p.vol, p.det, m, beta, p.ds, ACC32 ? p.round_interp : p.entry_interp);
     return hipGetLastError();
 }
 

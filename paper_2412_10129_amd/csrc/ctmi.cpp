@@ -70,6 +70,16 @@ int check_geometry(const ctmi_geometry* g, const double* angles, int64_t nviews)
     const int64_t nv = g->nDetector[0], nu = g->nDetector[1];
     if (nu > 4096 || nv > (1 << 20)) return fail(CTMI_EOVERFLOW, "detector must have nu <= 4096");
     if (nviews > (1 << 24)) return fail(CTMI_EOVERFLOW, "too many views");
+    {
+        // the interpolated projector's samples of one ray inside the volume
+        // (its diagonal over the step) must stay below 2^15
+        const double hmin = std::fmin(g->dVoxel[0], std::fmin(g->dVoxel[1], g->dVoxel[2]));
+        const double diag = std::sqrt((double)nx * nx * g->dVoxel[2] * g->dVoxel[2] +
+                                      (double)ny * ny * g->dVoxel[1] * g->dVoxel[1] +
+                                      (double)nz * nz * g->dVoxel[0] * g->dVoxel[0]);
+        if (diag / (g->accuracy * hmin) + 8.0 >= 32768.0)
+            return fail(CTMI_EOVERFLOW, "more than 2^15 interpolation samples per ray: raise accuracy");
+    }
     // the volume's circumscribed sphere, grown by one voxel, must lie strictly
     // between the source and the detector plane for every view
     double half2 = 0.0, off2 = 0.0, dmax = 0.0;
@@ -208,6 +218,17 @@ int launched(hipError_t e, const char* what) { return e == hipSuccess ? CTMI_OK 
 
 }  // namespace
 
+int ctmi::api_fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int ctmi::api_hip(hipError_t e, const char* what) { return hip_fail(e, what); }
+
 struct ctmi_plan : Plan {};
 
 extern "C" {
@@ -250,16 +271,22 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     p->det.nv = (int)geo->nDetector[0];
     p->det.nu = (int)geo->nDetector[1];
     p->ds = (float)(geo->accuracy * std::fmin(geo->dVoxel[0], std::fmin(geo->dVoxel[1], geo->dVoxel[2])));
-    // largest possible matrix entries, which size the adjoints' fixed-point
-    // scale: a Siddon entry is a chord of one cell (at most its diagonal); an
-    // interpolated entry is ds times the tent sum over the samples inside the
-    // 2x2x2 support (at most 2 diagonal / ds + 1 samples of weight <= 1)
+    // largest single contribution factors, which size the adjoints'
+    // fixed-point scale: one Siddon term is a chord of one cell (at most its
+    // diagonal); one interpolation term is a sample's tent weight (<= 1)
+    // times ds
     {
         double hdiag2 = 0.0;
         for (int a = 0; a < 3; ++a) hdiag2 += geo->dVoxel[a] * geo->dVoxel[a];
         const double hdiag = std::sqrt(hdiag2);
         p->entry_siddon = (float)(hdiag * 1.0001);
-        p->entry_interp = (float)((2.0 * hdiag + (double)p->ds) * 1.0001);
+        p->entry_interp = (float)((double)p->ds * 1.0001);
+        // samples of one ray inside a 2x2x2-voxel support: the chord is at most
+        // 2 sqrt(3) voxel units and samples are at least ds / h_max apart
+        // (one more for FP32 rounding of the positions)
+        const double hmax = std::fmax(geo->dVoxel[0], std::fmax(geo->dVoxel[1], geo->dVoxel[2]));
+        const double K = std::floor(2.0 * std::sqrt(3.0) * hmax / (double)p->ds) + 2.0;
+        p->round_interp = (float)(256.0 * K * (double)p->ds * 1.0001);
     }
     int L = 1, logL = 0;
     while (L < 2 * p->det.nu - 1 || L < 2) {

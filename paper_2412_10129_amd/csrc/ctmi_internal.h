@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/ctmi.h"
 
 namespace ctmi {
@@ -68,8 +70,9 @@ struct Plan {
     VolDims vol;
     DetDims det;
     float ds;             // interpolated-projector step, mm
-    float entry_siddon;   // largest possible matrix entry a_ij, Siddon (mm)
-    float entry_interp;   // the same for the interpolated projector (mm)
+    float entry_siddon;   // largest single adjoint term factor, Siddon (one chord, mm)
+    float entry_interp;   // the same for the interpolated projector (ds, mm)
+    float round_interp;   // bound on one round's sum into one cell over |y|: 256 K ds (mm)
 };
 
 // ------------------------------------------------------------ launchers
@@ -100,6 +103,69 @@ hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t
                               hipStream_t s);
 hipError_t launch_fov_sq_err(const Plan& p, const float* x, const float* gt, double* out, double* ws,
                              hipStream_t s);
+
+// ---------------------------------------------------------------- U-Net
+// Argument block of the 3x3x3 BF16 convolution (forward, and data gradient
+// with flipped weights).  Tensors are channels-last [n][d][h][w][ld].
+struct UnetConv3 {
+    const uint16_t* in0;
+    int c0, ld0;            // input channels [0, c0) from in0
+    const uint16_t* in1;
+    int c1, ld1;            // input channels [c0, c0 + c1) from in1 (c1 may be 0)
+    const uint16_t* wt;     // [cout][27][c0 + c1] BF16
+    const float* bias;      // [cout] or null
+    const uint16_t* mask;   // output multiplied by (mask > 0) when not null
+    int ldm;
+    uint16_t* out;
+    int ldo;
+    int cout, relu;
+    int n, d, h, w;
+};
+
+struct UnetWgrad {
+    const uint16_t* in0;
+    int c0, ld0;
+    const uint16_t* in1;
+    int c1, ld1;
+    const uint16_t* dz;     // output gradient [..][ldz], channels [0, cout)
+    int ldz;
+    int cout;
+    int n, d, h, w;
+    float* partial;         // workspace
+};
+
+hipError_t launch_unet_conv3(const UnetConv3& a, hipStream_t s);
+int unet_wgrad_splits(int n, int d, int h, int w, int cin, int cout);
+size_t unet_wgrad_ws_bytes(int n, int d, int h, int w, int cin, int cout);
+hipError_t launch_unet_conv3_wgrad(const UnetWgrad& a, float* dw, float* db, int accumulate, hipStream_t s);
+hipError_t launch_unet_pack_input(const float* x, int64_t nvox, uint16_t* out, hipStream_t s);
+hipError_t launch_unet_pool2(const uint16_t* in, int ldi, int n, int d, int h, int w, int c, uint16_t* out, int ldo,
+                             hipStream_t s);
+hipError_t launch_unet_skip_grad(const uint16_t* e, int lde, const uint16_t* dp, int ldp, const uint16_t* dcat,
+                                 int ldc, int n, int d, int h, int w, int c, uint16_t* out, int ldo, hipStream_t s);
+hipError_t launch_unet_up2(const uint16_t* x, int ldx, int cin, const uint16_t* wt, const float* bias, int cout,
+                           int n, int d, int h, int w, uint16_t* out, int ldo, hipStream_t s);
+hipError_t launch_unet_up2_dgrad(const uint16_t* g, int ldg, int cout, const uint16_t* wt, int cin,
+                                 const uint16_t* below, int ldb, int n, int d, int h, int w, uint16_t* out, int ldo,
+                                 hipStream_t s);
+size_t unet_up2_wgrad_ws_bytes(int n, int d, int h, int w, int cin, int cout);
+hipError_t launch_unet_up2_wgrad(const uint16_t* x, int ldx, int cin, const uint16_t* g, int ldg, int cout, int n,
+                                 int d, int h, int w, float* ws, float* dw, float* db, int accumulate, hipStream_t s);
+hipError_t launch_unet_head(const float* xin, const uint16_t* act, int lda, int c, const uint16_t* hw,
+                            const float* hb, int64_t nvox, float* out, hipStream_t s);
+size_t unet_head_ws_bytes();
+hipError_t launch_unet_head_loss_bwd(const float* out, const float* tgt, const uint16_t* act, int lda,
+                                     const uint16_t* hw, int64_t nvox, uint16_t* dz, int ldz, double* ws,
+                                     double* sums, float* dhead, hipStream_t s);
+hipError_t launch_unet_adam(float* w, float* m, float* v, const float* g, int64_t n, float b1, float b2, float lr_t,
+                            float inv_sqrt_bc2, float eps, hipStream_t s);
+hipError_t launch_unet_pack_conv3(const float* w, int cout, int cin, uint16_t* wf, uint16_t* wd, hipStream_t s);
+hipError_t launch_unet_to_bf16(const float* a, int64_t n, uint16_t* out, hipStream_t s);
+
+// error reporting shared by the entry points (thread-local message)
+int api_fail(int code, const char* fmt, ...);
+int api_hip(hipError_t e, const char* what);
+
 
 #ifdef __HIPCC__
 // ------------------------------------------------------------------------
@@ -226,34 +292,46 @@ struct InterpRay {
     int kc, k0, k1;
 };
 
+// Interpolated-projector ray of pixel (iu, iv): samples k sit at S + k ds d̂
+// in voxel-centre coordinates.  [k0, k1] holds every sample whose trilinear
+// support (-1, n) per axis can be entered, widened by one sample at each end
+// (those extra samples lie at most one step outside the support, where the
+// interpolant is 0, so they add nothing); kc = (k0 + k1) / 2 anchors the
+// FP32 positions base + (k - kc) st, with base formed in FP64.  The forward
+// projector and its transpose both call this function, so they visit the
+// same samples at the same FP32 positions.
 __device__ __forceinline__ bool interp_ray(const ViewGeo64& g, int iu, int iv, const VolDims& v, float ds,
                                            InterpRay& r)
 {
     double S[3], d[3];
     pixel_ray64(g, iu, iv, S, d);
     const double x = d[0] * v.hx, y = d[1] * v.hy, z = d[2] * v.hz;
-    const double L = __builtin_sqrt(__builtin_fma(x, x, __builtin_fma(y, y, z * z)));
-    const double sc = (double)ds / L;
+    const double L2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
+    // 1 / L: hardware estimate refined by two Newton steps (full FP64 accuracy)
+    double rl = __builtin_amdgcn_rsq(L2);
+    rl = rl * __builtin_fma(-0.5 * L2, rl * rl, 1.5);
+    rl = rl * __builtin_fma(-0.5 * L2, rl * rl, 1.5);
+    const double sc = (double)ds * rl;
     const int n[3] = {v.nx, v.ny, v.nz};
-    double kmin = 0.0, kmax = L / (double)ds;
+    float kmin = 0.0f, kmax = (float)(L2 * rl) / ds;
     double Sc[3], st[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         Sc[a] = S[a] - 0.5;
         st[a] = d[a] * sc;
-        if (st[a] != 0.0) {
-            const double inv = 1.0 / st[a];
-            const double ka = (-1.0 - Sc[a]) * inv;
-            const double kb = ((double)n[a] - Sc[a]) * inv;
-            kmin = fmax(kmin, fmin(ka, kb));
-            kmax = fmin(kmax, fmax(ka, kb));
-        } else if (!(Sc[a] > -1.0 && Sc[a] < (double)n[a])) {
+        const float stf = (float)st[a], Sf = (float)Sc[a];
+        if (stf != 0.0f) {
+            const float inv = __builtin_amdgcn_rcpf(stf);
+            const float ka = (-1.0f - Sf) * inv, kb = ((float)n[a] - Sf) * inv;
+            kmin = fmaxf(kmin, fminf(ka, kb));
+            kmax = fminf(kmax, fmaxf(ka, kb));
+        } else if (!(Sf > -1.0f && Sf < (float)n[a])) {
             return false;
         }
     }
-    if (!(kmin < kmax)) return false;
-    r.k0 = (int)__builtin_ceil(kmin);
-    r.k1 = (int)__builtin_floor(kmax);
+    if (!(kmin <= kmax + 2.0f)) return false;
+    r.k0 = (int)__builtin_ceilf(kmin) - 1;
+    r.k1 = (int)__builtin_floorf(kmax) + 1;
     if (r.k1 < r.k0) return false;
     r.kc = (r.k0 + r.k1) >> 1;
 #pragma unroll

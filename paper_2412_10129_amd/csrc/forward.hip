@@ -151,13 +151,15 @@ __device__ __forceinline__ void load_box(float* box, const float* __restrict__ v
     const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int r = (int)__builtin_floorf(((float)i + 0.5f) * r0);
-        const int lx = i - r * b.e[0];
+        const int lx = i - (int)__umul24(r, b.e[0]);
         const int lz = (int)__builtin_floorf(((float)r + 0.5f) * r1);
-        const int ly = r - lz * b.e[1];
+        const int ly = r - (int)__umul24(lz, b.e[1]);
         const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = b.o[2] + lz;
         float val = 0.0f;
+        // the volume has fewer than 2^31 voxels (checked at plan creation), so
+        // the linear index fits 32 bits
         if ((unsigned)gx < (unsigned)v.nx && (unsigned)gy < (unsigned)v.ny && (unsigned)gz < (unsigned)v.nz)
-            val = vol[((int64_t)gz * v.ny + gy) * v.nx + gx];
+            val = vol[(__umul24((unsigned)gz, (unsigned)v.ny) + (unsigned)gy) * (unsigned)v.nx + (unsigned)gx];
         box[i] = val;
     }
 }
@@ -380,13 +382,16 @@ __global__ void __launch_bounds__(256) k_forward_interp(const float* __restrict_
     __syncthreads();
 
     const int na = a == 0 ? v.nx : (a == 1 ? v.ny : v.nz);
-    // a sample's lower corner A = floor(pos_a) lies in [-1, n - 1]; slab s
-    // takes the samples before the plane s SLAB + SLAB - 1 (direction +) or
-    // from the plane s SLAB - 1 on (direction -), and stages planes
-    // [s SLAB - 2, s SLAB + SLAB] so a sample assigned one step early or late
-    // by rounding still finds its corners in the box
+    // a sample's lower corner A = floor(pos_a) lies in [-2, n] (the sample
+    // range reaches one step beyond the interpolant's support, and FP32
+    // positions may round across its edge); slab s takes the samples before
+    // the plane s SLAB + SLAB - 1 (direction +) or from the plane s SLAB - 1
+    // on (direction -), and stages planes [s SLAB - 2, s SLAB + SLAB] so a
+    // sample assigned one step early or late by rounding still finds its
+    // corners in the box.  Boxes may reach one plane of zeros beyond each
+    // halo plane, so every corner of such a sample is staged.
     const int nslab = (na + SLAB) / SLAB;
-    const int clo[3] = {-1, -1, -1}, chi[3] = {v.nx, v.ny, v.nz};
+    const int clo[3] = {-2, -2, -2}, chi[3] = {v.nx + 1, v.ny + 1, v.nz + 1};
 
     for (int si = 0; si < nslab; ++si) {
         const int s = dir > 0 ? si : nslab - 1 - si;

@@ -3,6 +3,7 @@ every symbol its header declares, validates arguments before touching the
 device, and computes the per-view geometry table consistently with the
 oracle's ray geometry."""
 import ctypes
+import glob
 import os
 import re
 
@@ -22,9 +23,11 @@ def ctmi():
 
 
 def _header_symbols():
-    src = open(os.path.join(ROOT, "include", "ctmi.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ctmi_[a-z0-9_]+)\s*\(", src)))
+    syms = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        syms |= set(re.findall(r"\b(ctmi_[a-z0-9_]+)\s*\(", src))
+    return sorted(syms)
 
 
 def test_library_exports_every_declared_symbol(ctmi):
@@ -35,6 +38,17 @@ def test_library_exports_every_declared_symbol(ctmi):
         assert hasattr(lib, s), s
     from paper_2412_10129_amd import _lib
     assert set(syms) == set(_lib.EXPORTED)
+
+
+def test_binding_argument_counts_match_headers():
+    """Every ctypes signature has as many arguments as the C declaration."""
+    from paper_2412_10129_amd import _lib
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for name, params in re.findall(r"\b(ctmi_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
+            params = params.strip()
+            n = 0 if params in ("", "void") else params.count(",") + 1
+            assert len(_lib._SIGS[name][1]) == n, (name, n, len(_lib._SIGS[name][1]))
 
 
 def test_version_and_error_string(ctmi):
