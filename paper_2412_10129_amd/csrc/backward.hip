@@ -13,16 +13,20 @@
 // block scan, and processed round-robin so rays of different lengths keep
 // every lane busy.
 //
-// Accumulation is in 64-bit fixed point in LDS: FP32 LDS atomics are
-// serialised on gfx950 (about 0.3 lane-ops per CU clock) while 64-bit
-// integer LDS atomics run about 30x faster.  Views are taken in groups of 8;
-// per (brick, group) the scale is the largest power of two that keeps every
-// single contribution a_ij y_i within an int32, from the footprints' max |y|
-// and the largest possible matrix entry (a resolution of 2^-31 of the largest
-// contribution, finer than FP32 rounding); the contributions are summed
-// exactly in the 64-bit accumulators, and after each group converted (exact
-// power-of-two scaling) into per-thread FP32 registers in group order.
-// Integer addition is associative, so the result is bit-reproducible.
+// Accumulation is in fixed point in LDS: FP32 LDS atomics are serialised
+// on gfx950 (about 0.3 lane-ops per CU clock) while integer LDS atomics run
+// 30-45x faster.  Views are taken in groups of 8.  Siddon (one atomic per
+// segment): one power-of-two scale per (brick, group) from the footprints'
+// max |y| keeps every contribution within an int32 at 2^-30 of the largest
+// one, and 64-bit cells sum the whole group exactly.  Interpolated (eight
+// atomics per sample): the scale is chosen per round of 256 rays so that
+// everything the round can add to one cell fits an int32 (one ray adds at
+// most K ds |y| to a cell, K the most samples of a ray inside a 2x2x2-voxel
+// support, so the bound is K ds sum |y| over the round's rays); 32-bit
+// cells (about 1.4x faster atomics) hold the round's exact integer sum and
+// are flushed after every round.  Flushes convert the integer sums (exact
+// power-of-two scaling) into per-thread FP32 registers in a fixed order;
+// integer addition is associative, so the result is bit-reproducible.
 #include "ctmi_internal.h"
 
 #include <type_traits>
@@ -38,7 +42,7 @@ namespace {
 #define CTMI_BWD_SID_CELLS 4
 #endif
 #ifndef CTMI_BWD_INT_SAMPLES
-#define CTMI_BWD_INT_SAMPLES 8
+#define CTMI_BWD_INT_SAMPLES 4
 #endif
 constexpr int BX = 16, BY = 16, BZ = CTMI_BWD_BZ;   // brick (voxels)
 constexpr int NB = BX * BY * BZ;
@@ -124,6 +128,18 @@ __device__ __forceinline__ void fill_item_map(unsigned char* map, int off, int c
 {
     const int e = min(off + cnt, MAPCAP);
     for (int i = off; i < e; ++i) map[i] = (unsigned char)threadIdx.x;
+}
+
+// Sum of one float per thread over a 256-thread block, in a fixed order
+// (deterministic).  `wsum` holds 4 floats of LDS; the call synchronises.
+__device__ __forceinline__ float block_sum(float v, float* wsum)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
 // Largest r in [0, 255] with pre[r] <= it (pre non-decreasing).
@@ -259,21 +275,43 @@ __device__ __forceinline__ void store_owned(float* __restrict__ vol, const float
     }
 }
 
+// Accumulator cells.  64-bit: each contribution is an int32 against the
+// per-(brick, group) scale and the cells hold the group's exact sums.
+// 32-bit: the scale is chosen per round so that everything the round's rays
+// can add to one cell fits (cmax sum_r |y_r|, cmax the most one ray adds to
+// one cell per unit y), the cells are flushed after every round, and
+// contributions are rounded to nearest; 32-bit LDS atomics run about 1.4x
+// faster than 64-bit ones.
+#ifndef CTMI_BWD_ACC32
+#define CTMI_BWD_ACC32 1
+#endif
+#ifndef CTMI_BWD_SID_ACC32
+#define CTMI_BWD_SID_ACC32 0
+#endif
+constexpr bool ACC32 = CTMI_BWD_ACC32 != 0;
+constexpr bool SID_ACC32 = CTMI_BWD_SID_ACC32 != 0;
+typedef std::conditional<ACC32, int, u64>::type IAcc;
+typedef std::conditional<SID_ACC32, int, u64>::type SAcc;
+
+__device__ __forceinline__ void acc_add(int* a, float q) { atomicAdd(a, (int)__builtin_rintf(q)); }
+__device__ __forceinline__ void acc_add(u64* a, float q) { atomicAdd(a, to_fixed(q)); }
+
 constexpr int SID_CELLS = CTMI_BWD_SID_CELLS;   // dominant-axis cells per Siddon item
 
-__global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
                                                          const ViewGeo64* __restrict__ tab64, int view0, int nviews,
                                                          VolDims v, DetDims det, BrickMap m, float beta, float cmax)
 {
-    __shared__ u64 acc[NB];
+    __shared__ SAcc acc[NB];
     __shared__ float t_S[3][256], t_d[3][256];
     __shared__ float t_a0[256], t_a1[256], t_y[256];
     __shared__ int t_c0[256], t_nc[256], t_pre[256];
     __shared__ unsigned char imap[MAPCAP];
     __shared__ int wsum[4];
+    __shared__ float wsumf[4];
     __shared__ GroupLds G;
-    for (int i = threadIdx.x; i < NB; i += blockDim.x) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < NB; i += blockDim.x) acc[i] = 0;
     float own[OWN];
 #pragma unroll
     for (int i = 0; i < OWN; ++i) own[i] = 0.0f;
@@ -290,13 +328,16 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
         __syncthreads();
         const int npx = make_group(G, tab, view0, k, ng, lo, hi, det);
         if (npx == 0) continue;
-        const float maxy = group_max(G, proj, det, k, npx);
+        // 64-bit cells: one scale per group from the largest |y| of its
+        // footprints; 32-bit cells: one scale per round (below)
+        const float maxy = SID_ACC32 ? 1.0f : group_max(G, proj, det, k, npx);
         if (!(maxy > 0.0f)) continue;
         float inv;
-        const float scale = fixed_scale(cmax, maxy, &inv);
+        float scale = SID_ACC32 ? 0.0f : fixed_scale(cmax, maxy, &inv);
         for (int p0 = 0; p0 < npx; p0 += 256) {
             const int p = p0 + tid;
             int cnt = 0;
+            float yr = 0.0f, yl_ = 0.0f;   // this ray's y, and y times its world length
             if (p < npx) {
                 int gv, iu, iv;
                 group_pixel(G, p, gv, iu, iv);
@@ -333,12 +374,25 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
                         t_a1[tid] = amax;
                         t_c0[tid] = c0 * 4 + dom;
                         t_nc[tid] = nc;
-                        t_y[tid] = pk[(int64_t)iv * det.nu + iu] * world_length(d, v) * scale;
+                        yr = pk[(int64_t)iv * det.nu + iu];
+                        yl_ = yr * world_length(d, v);
                     }
                 }
             }
             int total;
             const int off = block_scan(cnt, wsum, &total);
+            if (SID_ACC32) {
+                // a ray crosses a cell once (items end on cell boundaries), so
+                // one cell's round sum is at most cmax sum_r |y_r| (cmax: the
+                // longest chord of a cell)
+                const float ysum = block_sum(cnt > 0 ? fabsf(yr) : 0.0f, wsumf);
+                if (!(ysum > 0.0f)) {
+                    __syncthreads();
+                    continue;
+                }
+                scale = fixed_scale(cmax, ysum, &inv);
+            }
+            if (cnt > 0) t_y[tid] = yl_ * scale;
             t_pre[tid] = off;
             __syncthreads();
             fill_item_map(imap, off, cnt);
@@ -382,7 +436,7 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
                 for (int step = 0; step < BX + BY + BZ + 3; ++step) {
                     const float an = fminf(anx, fminf(any, anz));
                     const float ae = fminf(an, aend);
-                    atomicAdd(&acc[li], to_fixed(fmaxf(ae - acur, 0.0f) * yl));
+                    acc_add(&acc[li], fmaxf(ae - acur, 0.0f) * yl);
                     if (an >= aend) break;
                     acur = an;
                     if (an == anx) {
@@ -407,37 +461,22 @@ __global__ void __launch_bounds__(256) k_backward_siddon(const float* __restrict
                 }
             }
             __syncthreads();
+            if (SID_ACC32) {
+                // 32-bit cells hold one round's sums (bounded by the scale)
+                flush_view(acc, NB, BX, BY, 0, inv, own);
+                __syncthreads();
+            }
         }
-        flush_view(acc, NB, BX, BY, 0, inv, own);
-        __syncthreads();
+        if (!SID_ACC32) {
+            flush_view(acc, NB, BX, BY, 0, inv, own);
+            __syncthreads();
+        }
     }
     store_owned(vol, own, v, x0, y0, z0, beta);
 }
 
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;   // interpolated accumulator: brick plus a one-voxel halo
 constexpr int INT_SAMPLES = CTMI_BWD_INT_SAMPLES;  // samples per interpolated item
-
-// Accumulator cells of the interpolated adjoint.  64-bit: each contribution
-// is an int32 against the per-(brick, group) scale and the cells hold the
-// group's exact sums.  32-bit (ACC32): the scale also covers every term one
-// round of 256 rays can add to one cell (the plan's factor 256 K, K the most
-// samples of one ray inside a 2x2x2-voxel support), the cells are flushed
-// after every round, and contributions are rounded to nearest; 32-bit LDS
-// atomics run about 1.4x faster than 64-bit ones.
-#ifndef CTMI_BWD_ACC32
-#define CTMI_BWD_ACC32 0
-#endif
-constexpr bool ACC32 = CTMI_BWD_ACC32 != 0;
-typedef std::conditional<ACC32, int, u64>::type IAcc;
-
-__device__ __forceinline__ void iacc_add(IAcc* a, float q)
-{
-    if constexpr (ACC32) {
-        atomicAdd(a, (int)__builtin_rintf(q));
-    } else {
-        atomicAdd(a, to_fixed(q));
-    }
-}
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
@@ -454,6 +493,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     __shared__ int t_pre[256];
     __shared__ unsigned char imap[MAPCAP];
     __shared__ int wsum[4];
+    __shared__ float wsumf[4];
     __shared__ GroupLds G;
     for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0;
     float own[OWN];
@@ -482,13 +522,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         __syncthreads();
         const int npx = make_group(G, tab, view0, k, ng, lo, hi, det);
         if (npx == 0) continue;
-        const float maxy = group_max(G, proj, det, k, npx);
+        // 64-bit cells: one scale per group from the largest |y| of its
+        // footprints; 32-bit cells: one scale per round (below)
+        const float maxy = ACC32 ? 1.0f : group_max(G, proj, det, k, npx);
         if (!(maxy > 0.0f)) continue;
         float inv;
-        const float scale = fixed_scale(cmax, maxy, &inv);
+        float scale = ACC32 ? 0.0f : fixed_scale(cmax, maxy, &inv);
         for (int p0 = 0; p0 < npx; p0 += 256) {
             const int p = p0 + tid;
             int cnt = 0;
+            float yr = 0.0f;   // this ray's y
             if (p < npx) {
                 int gv, iu, iv;
                 group_pixel(G, p, gv, iu, iv);
@@ -522,8 +565,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                             // because a ray has fewer than 2^15 samples in the
                             // volume (checked at plan creation)
                             const int jn = ((ks - ray.kc) & 0xFFFF) | (n << 16);
-                            t_a[tid] = make_float4(ray.base[0], ray.base[1], ray.base[2],
-                                                   pk[(int64_t)iv * det.nu + iu] * ds * scale);
+                            yr = pk[(int64_t)iv * det.nu + iu];
+                            t_a[tid] = make_float4(ray.base[0], ray.base[1], ray.base[2], 0.0f);
                             t_b[tid] = make_float4(ray.st[0], ray.st[1], ray.st[2], __int_as_float(jn));
                         }
                     }
@@ -531,6 +574,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             }
             int total;
             const int off = block_scan(cnt, wsum, &total);
+            if (ACC32) {
+                // one cell's round sum is at most cmax sum_r |y_r| (cmax: K
+                // samples of ds, K the most samples of one ray inside a
+                // 2x2x2-voxel support)
+                const float ysum = block_sum(cnt > 0 ? fabsf(yr) : 0.0f, wsumf);
+                if (!(ysum > 0.0f)) {
+                    __syncthreads();
+                    continue;
+                }
+                scale = fixed_scale(cmax, ysum, &inv);
+            }
+            if (cnt > 0) t_a[tid].w = yr * ds * scale;
             t_pre[tid] = off;
             __syncthreads();
             fill_item_map(imap, off, cnt);
@@ -573,14 +628,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     const float w01 = (1.0f - ay_) * yz1, w11 = ay_ * yz1;
                     const float bx0 = 1.0f - ax_;
                     IAcc* a0 = reinterpret_cast<IAcc*>(accb + boff);
-                    iacc_add(a0, bx0 * w00);
-                    iacc_add(a0 + 1, ax_ * w00);
-                    iacc_add(a0 + HX, bx0 * w10);
-                    iacc_add(a0 + HX + 1, ax_ * w10);
-                    iacc_add(a0 + HX * HY, bx0 * w01);
-                    iacc_add(a0 + HX * HY + 1, ax_ * w01);
-                    iacc_add(a0 + HX * HY + HX, bx0 * w11);
-                    iacc_add(a0 + HX * HY + HX + 1, ax_ * w11);
+                    acc_add(a0, bx0 * w00);
+                    acc_add(a0 + 1, ax_ * w00);
+                    acc_add(a0 + HX, bx0 * w10);
+                    acc_add(a0 + HX + 1, ax_ * w10);
+                    acc_add(a0 + HX * HY, bx0 * w01);
+                    acc_add(a0 + HX * HY + 1, ax_ * w01);
+                    acc_add(a0 + HX * HY + HX, bx0 * w11);
+                    acc_add(a0 + HX * HY + HX + 1, ax_ * w11);
                 }
             }
             __syncthreads();
@@ -615,7 +670,7 @@ hipError_t launch_backward_siddon(const Plan& p, const float* proj, float* vol, 
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_siddon, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.entry_siddon);
+                       (int)nviews, p.vol, p.det, m, beta, SID_ACC32 ? p.round_siddon : p.entry_siddon);
     return hipGetLastError();
 }
 

@@ -280,13 +280,16 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
         for (int a = 0; a < 3; ++a) hdiag2 += geo->dVoxel[a] * geo->dVoxel[a];
         const double hdiag = std::sqrt(hdiag2);
         p->entry_siddon = (float)(hdiag * 1.0001);
+        // one ray crosses a cell once, and items end on cell boundaries, so a
+        // ray adds at most one chord to one cell
+        p->round_siddon = (float)(hdiag * 1.0001);
         p->entry_interp = (float)((double)p->ds * 1.0001);
         // samples of one ray inside a 2x2x2-voxel support: the chord is at most
         // 2 sqrt(3) voxel units and samples are at least ds / h_max apart
         // (one more for FP32 rounding of the positions)
         const double hmax = std::fmax(geo->dVoxel[0], std::fmax(geo->dVoxel[1], geo->dVoxel[2]));
         const double K = std::floor(2.0 * std::sqrt(3.0) * hmax / (double)p->ds) + 2.0;
-        p->round_interp = (float)(256.0 * K * (double)p->ds * 1.0001);
+        p->round_interp = (float)(K * (double)p->ds * 1.0001);
     }
     int L = 1, logL = 0;
     while (L < 2 * p->det.nu - 1 || L < 2) {

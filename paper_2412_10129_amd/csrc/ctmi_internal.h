@@ -72,7 +72,8 @@ struct Plan {
     float ds;             // interpolated-projector step, mm
     float entry_siddon;   // largest single adjoint term factor, Siddon (one chord, mm)
     float entry_interp;   // the same for the interpolated projector (ds, mm)
-    float round_interp;   // bound on one round's sum into one cell over |y|: 256 K ds (mm)
+    float round_interp;   // most one ray adds to one adjoint cell per unit y: K ds (mm)
+    float round_siddon;   // the same for Siddon: one chord (mm)
 };
 
 // ------------------------------------------------------------ launchers
