@@ -80,7 +80,7 @@ def profile_summary(db_path, top=12):
     import re
     import sqlite3
     con = sqlite3.connect(db_path)
-    short = lambda n: re.split(r"[(<]", n.replace("ctmi::(anonymous namespace)::", ""))[0].strip()
+    short = lambda n: re.sub(r"^void ", "", n.replace("ctmi::(anonymous namespace)::", "").split("(")[0]).strip()
     lines = []
     tables = {r[0] for r in con.execute("select name from sqlite_master where type in ('table', 'view')")}
     if "top_kernels" in tables:

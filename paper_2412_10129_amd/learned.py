@@ -18,6 +18,7 @@ the full circle, noiseless data from the same projector that reconstructs):
 Command line (writes JSON / checkpoints where told):
     python -m paper_2412_10129_amd.learned train --phantoms 32 --steps 1500 --out ckpt.pt
     python -m paper_2412_10129_amd.learned evaluate --ckpt ckpt.pt --phantoms 4 --iters 60
+    python -m paper_2412_10129_amd.learned bench
 """
 from __future__ import annotations
 
@@ -147,6 +148,47 @@ def evaluate(plan: Plan, net: UNet, vols: List[np.ndarray], niter: int = 60, eve
     return {"runs": runs, "niter": niter, "every": every, "ratio": ratio, "kind": kind, "target_db": target_db}
 
 
+def bench_unet(repeat: int = 3, log=print) -> List[Dict]:
+    """Forward and training-step times (ms, GPU events) of the U-Net on one
+    256^3 volume and on a batch of four 64^3 crops; FLOP/s from the
+    network's multiply-adds (3x3x3 and 2x2x2 convolutions, 2 flops each)."""
+    net = UNet(seed=0)
+    out = []
+    for shape in [(1, 256, 256, 256), (4, 64, 64, 64)]:
+        x = torch.rand(shape, device=net.device, generator=torch.Generator(device=net.device).manual_seed(0))
+        tgt = x * 0.9
+        res = {"shape": list(shape)}
+        for name, fn in (("fwd_ms", lambda: net.forward(x)), ("train_ms", lambda: net.train_step(x, tgt))):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(repeat):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[name] = round(e0.elapsed_time(e1) / repeat, 3)
+        res["fwd_TFLOP/s"] = round(unet_flops(shape, net.ch) / (res["fwd_ms"] / 1e3) / 1e12, 1)
+        log(json.dumps(res))
+        out.append(res)
+    return out
+
+
+def unet_flops(shape, channels) -> float:
+    """Multiply-add flops of one forward pass (convolutions only)."""
+    n, d, h, w = shape
+    vox = float(n * d * h * w)
+    fl, cin = 0.0, 1            # algorithmic: the first convolution has one input channel
+    for lvl, c in enumerate(channels):
+        v = vox / 8 ** lvl
+        fl += 2 * 27 * v * (cin * c + c * c)
+        cin = c
+    for lvl in range(len(channels) - 2, -1, -1):
+        c, v = channels[lvl], vox / 8 ** lvl
+        fl += 2 * v * channels[lvl + 1] * c                 # up-convolution: one tap per output voxel
+        fl += 2 * 27 * v * (2 * c * c + c * c)
+    return fl
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -167,8 +209,13 @@ def main(argv=None):
     e.add_argument("--kind", default="interp")
     e.add_argument("--out", default=None)
     e.add_argument("--workers", type=int, default=8)
+    b = sub.add_parser("bench", help="time the U-Net forward and one training step")
+    b.add_argument("--repeat", type=int, default=3)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
+    if a.cmd == "bench":
+        bench_unet(a.repeat, log)
+        return
     geo, ang = synth.workload("sparse256")
     plan = Plan(geo, ang)
     if a.cmd == "train":
