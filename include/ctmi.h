@@ -27,10 +27,13 @@
  * aligned, owned by the caller.  The library never allocates or frees per
  * call and keeps no pointer after a call returns.  Every call is
  * asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
- * returns after enqueueing its kernels.  A plan owns a small device table
- * (per-view geometry and filter coefficients) allocated on the device that
- * is current when the plan is created; calls must run with that device
- * current.
+ * returns after enqueueing its kernels.  A plan owns one device allocation
+ * made on the device that is current when the plan is created: the per-view
+ * geometry and filter tables, and the interpolated adjoint's brick-shell
+ * buffer (553 floats per 16x16x8 voxel brick, about 27 % of the volume's
+ * size).  Calls must run with that device current, and interpolated
+ * backprojections that share a plan must not run concurrently (they share
+ * the shell buffer); every other call may.
  *
  * Errors: every call returns CTMI_OK (0) or a negative code; argument checks
  * happen before anything is enqueued, so a failing call has no effect.

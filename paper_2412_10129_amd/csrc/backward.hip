@@ -478,15 +478,70 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2;   // interpolated accumulator: brick plus a one-voxel halo
 constexpr int INT_SAMPLES = CTMI_BWD_INT_SAMPLES;  // samples per interpolated item
 
+// Each interpolation sample is processed once, by the brick that holds its
+// lower corner (the first brick of an axis also takes corners at -1, whose
+// cell lies outside the volume).  Its upper corners may fall one voxel past
+// the brick: those cells form the brick's upper shell, 553 cells in three
+// faces (x = BX with y, z in [0, BY] x [0, BZ]; y = BY with x < BX; z = BZ
+// with x < BX, y < BY), written to the plan's halo buffer and added to the
+// neighbouring bricks' voxels by k_halo_add in a fixed order.
+constexpr int HSX = (BY + 1) * (BZ + 1), HSY = BX * (BZ + 1), HSZ = BX * BY;
+constexpr int HALO_SLOTS = HSX + HSY + HSZ;
+constexpr int NH = (HALO_SLOTS + 255) / 256;   // shell cells per thread
+static_assert(HALO_SLOTS == CTMI_HALO_SLOTS, "halo buffer size");
+
+__device__ __forceinline__ void halo_slot(int h, int& lx, int& ly, int& lz)
+{
+    if (h < HSX) {
+        lx = BX;
+        ly = h % (BY + 1);
+        lz = h / (BY + 1);
+    } else if (h < HSX + HSY) {
+        h -= HSX;
+        lx = h % BX;
+        ly = BY;
+        lz = h / BX;
+    } else {
+        h -= HSX + HSY;
+        lx = h % BX;
+        ly = h / BX;
+        lz = BZ;
+    }
+}
+
+// shell cells -> per-thread FP32 registers (accumulator origin at the brick
+// corner minus one voxel)
+template <typename Acc>
+__device__ __forceinline__ void flush_shell(const Acc* acc, float inv, float hown[NH])
+{
+#pragma unroll
+    for (int m = 0; m < NH; ++m) {
+        const int h = threadIdx.x + 256 * m;
+        if (h < HALO_SLOTS) {
+            int lx, ly, lz;
+            halo_slot(h, lx, ly, lz);
+            const Acc a = acc[((lz + 1) * HY + (ly + 1)) * HX + (lx + 1)];
+            hown[m] = __builtin_fmaf((float)(long long)a, inv, hown[m]);
+        }
+    }
+}
+
+#ifndef CTMI_BWD_HALO
+#define CTMI_BWD_HALO 1
+#endif
+constexpr bool HALO = CTMI_BWD_HALO != 0;
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
                                                          const ViewGeo64* __restrict__ tab64, int view0, int nviews,
                                                          VolDims v, DetDims det, BrickMap m, float beta, float ds,
-                                                         float cmax)
+                                                         float cmax, float* __restrict__ shell)
 {
-    // accumulator over voxels [b0 - 1, b1] per axis; the halo takes the
-    // corners that fall outside the brick and is discarded, so every sample
-    // scatters to 8 fixed offsets without per-corner tests
+    // accumulator over voxels [b0 - 1, b1] per axis, so every sample scatters
+    // to 8 fixed offsets without per-corner tests; the lower face holds
+    // corners outside the volume (discarded), the upper shell goes to the
+    // neighbours (or, without HALO, is discarded and the neighbours
+    // recompute those samples)
     __shared__ IAcc acc[HX * HY * HZ];
     // ray table: (base, y) and (st, first sample | sample count << 16)
     __shared__ float4 t_a[256], t_b[256];
@@ -496,24 +551,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     __shared__ float wsumf[4];
     __shared__ GroupLds G;
     for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0;
-    float own[OWN];
+    float own[OWN], hown[NH];
 #pragma unroll
     for (int i = 0; i < OWN; ++i) own[i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NH; ++i) hown[i] = 0.0f;
     int bx, by, bz;
     brick_origin(m, blockIdx.x, bx, by, bz);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
     const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
-    // samples that touch voxels [x0, x1) lie in the open box (x0 - 1, x1) of
-    // voxel-centre coordinates
-    const float lo[3] = {x0 - 1.0f, y0 - 1.0f, z0 - 1.0f};
+    // HALO: the brick takes samples whose lower corner lies in [x0, x1) (from
+    // -1 for the first brick of an axis); otherwise every sample touching
+    // voxels [x0, x1), i.e. lower corner in [x0 - 1, x1).  Positions of those
+    // samples lie in [lo, hi) (voxel-centre coordinates).
+    const float lo[3] = {(HALO && x0 > 0) ? (float)x0 : x0 - 1.0f, (HALO && y0 > 0) ? (float)y0 : y0 - 1.0f,
+                         (HALO && z0 > 0) ? (float)z0 : z0 - 1.0f};
     const float hi[3] = {(float)x1, (float)y1, (float)z1};
     // a sample's lower corner (floor of its position) must lie in
     // [lo, hi - 1] per axis; the accumulator's byte offset of corner c is
-    // 8 ((c_z - lo_z) HX HY + (c_y - lo_y) HX + (c_x - lo_x)), formed in FP32
-    // (integers below 2^24)
+    // AB ((c_z - z0 + 1) HX HY + (c_y - y0 + 1) HX + (c_x - x0 + 1)), formed
+    // in FP32 (integers below 2^24)
     const float cmx = hi[0] - 1.0f, cmy = hi[1] - 1.0f, cmz = hi[2] - 1.0f;
     constexpr float AB = (float)sizeof(IAcc);   // accumulator bytes per cell
-    const float aoff = -AB * (lo[2] * (float)(HX * HY) + lo[1] * (float)HX + lo[0]);
+    const float aoff =
+        -AB * ((float)(z0 - 1) * (float)(HX * HY) + (float)(y0 - 1) * (float)HX + (float)(x0 - 1));
     const int tid = threadIdx.x;
     char* const accb = reinterpret_cast<char*>(acc);
 
@@ -641,16 +702,55 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             __syncthreads();
             if (ACC32) {
                 // 32-bit cells hold one round's sums (bounded by the scale)
+                if (HALO) flush_shell(acc, inv, hown);
                 flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
                 __syncthreads();
             }
         }
         if (!ACC32) {
+            if (HALO) flush_shell(acc, inv, hown);
             flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
             __syncthreads();
         }
     }
     store_owned(vol, own, v, x0, y0, z0, beta);
+    if (HALO) {
+        float* out = shell + (size_t)blockIdx.x * HALO_SLOTS;
+#pragma unroll
+        for (int m2 = 0; m2 < NH; ++m2) {
+            const int h = threadIdx.x + 256 * m2;
+            if (h < HALO_SLOTS) out[h] = hown[m2];
+        }
+    }
+}
+
+// Adds the upper shells of the lower neighbour bricks to the voxels on each
+// brick's lower faces, in a fixed order (x, y, z, xy, xz, yz, xyz
+// neighbours).
+__global__ void k_halo_add(float* __restrict__ vol, const float* __restrict__ shell, VolDims v, BrickMap m)
+{
+    const int64_t n = (int64_t)v.nx * v.ny * v.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int gx = (int)(i % v.nx);
+    const int64_t r = i / v.nx;
+    const int gy = (int)(r % v.ny), gz = (int)(r / v.ny);
+    const int bx = gx / BX, by = gy / BY, bz = gz / BZ;
+    const int lx = gx - bx * BX, ly = gy - by * BY, lz = gz - bz * BZ;
+    if (lx != 0 && ly != 0 && lz != 0) return;
+    auto cell = [&](int ex, int ey, int ez, int slot) {
+        return shell[((size_t)((ez * m.nby + ey) * m.nbx + ex)) * HALO_SLOTS + slot];
+    };
+    const bool X = lx == 0 && bx > 0, Y = ly == 0 && by > 0, Z = lz == 0 && bz > 0;
+    float add = 0.0f;
+    if (X) add += cell(bx - 1, by, bz, ly + (BY + 1) * lz);
+    if (Y) add += cell(bx, by - 1, bz, HSX + lx + BX * lz);
+    if (Z) add += cell(bx, by, bz - 1, HSX + HSY + lx + BX * ly);
+    if (X && Y) add += cell(bx - 1, by - 1, bz, BY + (BY + 1) * lz);
+    if (X && Z) add += cell(bx - 1, by, bz - 1, ly + (BY + 1) * BZ);
+    if (Y && Z) add += cell(bx, by - 1, bz - 1, HSX + lx + BX * BZ);
+    if (X && Y && Z) add += cell(bx - 1, by - 1, bz - 1, BY + (BY + 1) * BZ);
+    if (X || Y || Z) vol[i] += add;
 }
 
 BrickMap brick_map(const Plan& p)
@@ -680,7 +780,11 @@ hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, 
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.ds, ACC32 ? p.round_interp : p.entry_interp);
+                       (int)nviews, p.vol, p.det, m, beta, p.ds, ACC32 ? p.round_interp : p.entry_interp, p.d_halo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !HALO) return e;
+    const int64_t n = (int64_t)p.vol.nx * p.vol.ny * p.vol.nz;
+    hipLaunchKernelGGL(k_halo_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vol, p.d_halo, p.vol, m);
     return hipGetLastError();
 }
 

@@ -314,8 +314,12 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     const size_t t64b = sizeof(ctmi::ViewGeo64) * (size_t)nviews;
     const size_t hb = sizeof(float) * (size_t)L;
     const size_t wb = sizeof(float) * (size_t)L;  // L/2 float2
+    // upper shells of the interpolated adjoint's 16x16x8 voxel bricks
+    const size_t nbricks = (size_t)((p->vol.nx + 15) / 16) * ((p->vol.ny + 15) / 16) * ((p->vol.nz + 7) / 8);
+    const size_t sb = sizeof(float) * nbricks * CTMI_HALO_SLOTS;
+    const size_t sof = (tb + t64b + hb + wb + 255) / 256 * 256;
     char* mem = nullptr;
-    e = hipMalloc(reinterpret_cast<void**>(&mem), tb + t64b + hb + wb);
+    e = hipMalloc(reinterpret_cast<void**>(&mem), sof + sb);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "hipMalloc(plan tables)");
@@ -324,6 +328,7 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     p->d_views64 = reinterpret_cast<ctmi::ViewGeo64*>(mem + tb);
     p->d_filter = reinterpret_cast<float*>(mem + tb + t64b);
     p->d_twiddle = reinterpret_cast<float2*>(mem + tb + t64b + hb);
+    p->d_halo = reinterpret_cast<float*>(mem + sof);
     if ((e = hipMemcpy(p->d_views, t.data(), tb, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_views64, t64.data(), t64b, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_filter, Hbr.data(), hb, hipMemcpyHostToDevice)) != hipSuccess ||

@@ -47,6 +47,9 @@ struct ViewGeo64 {
 };
 static_assert(sizeof(ViewGeo64) == 128, "FP64 view table row must be 128 bytes");
 
+// Cells in the upper shell of one 16x16x8 adjoint brick (faces x, y, z).
+#define CTMI_HALO_SLOTS (17 * 9 + 16 * 9 + 16 * 16)
+
 struct VolDims {
     int nx, ny, nz;
     float hx, hy, hz;  // voxel size, mm
@@ -74,6 +77,7 @@ struct Plan {
     float entry_interp;   // the same for the interpolated projector (ds, mm)
     float round_interp;   // most one ray adds to one adjoint cell per unit y: K ds (mm)
     float round_siddon;   // the same for Siddon: one chord (mm)
+    float* d_halo;        // interpolated adjoint: CTMI_HALO_SLOTS floats per voxel brick
 };
 
 // ------------------------------------------------------------ launchers

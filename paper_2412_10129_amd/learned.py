@@ -148,6 +148,42 @@ def evaluate(plan: Plan, net: UNet, vols: List[np.ndarray], niter: int = 60, eve
     return {"runs": runs, "niter": niter, "every": every, "ratio": ratio, "kind": kind, "target_db": target_db}
 
 
+def quick_benchmark(train_phantoms: int = 4, steps: int = 600, test_phantoms: int = 2, niter: int = 60,
+                    kind: str = "interp", workers: int = 8, log=print) -> Dict:
+    """A bounded run of the whole learned-prior pipeline for the benchmark:
+    pairs from `train_phantoms` phantoms (seeds 0..), `steps` Adam steps,
+    then plain CGLS and PnP-CGLS on `test_phantoms` test volumes (seeds
+    10000..).  Returns per-volume times to 40 dB and to plain CGLS's best."""
+    t0 = time.perf_counter()
+    geo, ang = synth.workload("sparse256")
+    plan = Plan(geo, ang)
+    dense = Plan(geo, synth.circular_angles(720))
+    vols = phantoms("sparse256", range(train_phantoms), workers)
+    inputs, targets = make_pairs(plan, dense, vols, kind)
+    del dense
+    net = UNet(seed=0)
+    train(net, inputs, targets, steps, log=lambda m: None)
+    del inputs, targets
+    test = phantoms("sparse256", range(10000, 10000 + test_phantoms), workers)
+    res = evaluate(plan, net, test, niter, kind=kind, log=log)
+    rr = res["runs"]
+    out = {
+        "metric": "time to 40 dB PSNR, PnP-CGLS (learned prior) vs plain CGLS",
+        "unit": "ms",
+        "config": {"workload": "sparse256", "volume": list(geo.nVoxel), "views": len(ang), "projector": kind,
+                   "train_phantoms": train_phantoms, "train_pairs": 4 * train_phantoms, "train_steps": steps,
+                   "test_phantoms": test_phantoms, "iterations": niter, "denoise_every": 5},
+        "cgls_ms_to_40db": [r["cgls"]["ms_to_target"] for r in rr],
+        "pnp_ms_to_40db": [r["pnp"]["ms_to_target"] for r in rr],
+        "cgls_best_db": [round(r["cgls"]["best_psnr"], 3) for r in rr],
+        "pnp_best_db": [round(r["pnp"]["best_psnr"], 3) for r in rr],
+        "cgls_ms_to_cgls_best": [r["cgls"]["ms_to_cgls_best"] for r in rr],
+        "pnp_ms_to_cgls_best": [r["pnp"]["ms_to_cgls_best"] for r in rr],
+        "wall_s": round(time.perf_counter() - t0, 1),
+    }
+    return out
+
+
 def bench_unet(repeat: int = 3, log=print) -> List[Dict]:
     """Forward and training-step times (ms, GPU events) of the U-Net on one
     256^3 volume and on a batch of four 64^3 crops; FLOP/s from the
