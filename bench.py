@@ -8,7 +8,9 @@ updates per second: 2 * N^3 * views / step time.
 
 After the timed steps each operator (Siddon A and A^T, interpolated A and
 A^T, FDK filter, FDK backprojector) is timed on its own for the breakdown,
-and the FP64 CPU oracle is timed on a one-view sample of the same workload.
+a bounded learned-prior run measures the metric's second half (time to
+40 dB of PnP-CGLS with the U-Net against plain CGLS, sparse-view 256^3), and
+the FP64 CPU oracle is timed on a one-view sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--projector interp|siddon]
 """
@@ -186,6 +188,8 @@ def main():
     ap.add_argument("--projector", default="interp", choices=["interp", "siddon"])
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-prior run (training pairs, training, PnP-CGLS vs CGLS)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", metavar="DB",
@@ -334,6 +338,15 @@ def main():
             breakdown[name] = ent
             print(f"[bench] {name}: {ent}", flush=True)
 
+    learned = None
+    if not args.no_learned:
+        # the second half of the headline metric: time to 40 dB of the learned
+        # prior inside CGLS against plain CGLS (a bounded training run)
+        print("[bench] learned prior: pairs, training, PnP-CGLS vs CGLS ...", flush=True)
+        from paper_2412_10129_amd import learned as LN
+        learned = LN.quick_benchmark(log=lambda m: print(f"[bench] {m}", flush=True))
+        print(f"[bench] learned: {learned['wall_s']} s", flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on one view ...", flush=True)
@@ -358,6 +371,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "breakdown": breakdown,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 
