@@ -6,12 +6,12 @@
 // and accumulates it over every view of the call; each voxel has one writer
 // in global memory and no global atomics are used.  For a group of views, the
 // brick's detector footprints (bounding boxes of its projected corners) are
-// enumerated in rounds of 256 pixels: each thread re-traces one pixel's ray inside the
-// brick, with the same FP32 arithmetic as the forward kernel (shared helpers
-// in ctmi_internal.h), and records it in an LDS ray table; the rays' work is
-// cut into items of bounded size (a few cells or samples), numbered by a
-// block scan, and processed round-robin so rays of different lengths keep
-// every lane busy.
+// enumerated in rounds of 256 (Siddon) or 512 (interpolated) pixels: each
+// thread re-traces one or two pixels' rays inside the brick, with the same
+// FP32 arithmetic as the forward kernel (shared helpers in ctmi_internal.h),
+// and records them in an LDS ray table; the rays' work is cut into items of
+// bounded size (a few cells or samples), numbered by a block scan, and
+// processed round-robin so rays of different lengths keep every lane busy.
 //
 // Accumulation is in fixed point in LDS: FP32 LDS atomics are serialised
 // on gfx950 (about 0.3 lane-ops per CU clock) while integer LDS atomics run
@@ -19,7 +19,7 @@
 // segment): one power-of-two scale per (brick, group) from the footprints'
 // max |y| keeps every contribution within an int32 at 2^-30 of the largest
 // one, and 64-bit cells sum the whole group exactly.  Interpolated (eight
-// atomics per sample): the scale is chosen per round of 256 rays so that
+// atomics per sample): the scale is chosen per round of 512 rays so that
 // everything the round can add to one cell fits an int32 (one ray adds at
 // most K ds |y| to a cell, K the most samples of a ray inside a 2x2x2-voxel
 // support, so the bound is K ds sum |y| over the round's rays); 32-bit
@@ -27,6 +27,10 @@
 // are flushed after every round.  Flushes convert the integer sums (exact
 // power-of-two scaling) into per-thread FP32 registers in a fixed order;
 // integer addition is associative, so the result is bit-reproducible.
+//
+// The interpolated adjoint's rounds are latency-bound as much as
+// arithmetic-bound (a round costs barriers, a block scan and a flush), so a
+// round takes two rays per thread and needs three barriers.
 #include "ctmi_internal.h"
 
 #include <type_traits>
@@ -118,6 +122,27 @@ __device__ __forceinline__ int block_scan(int v, int* wsum, int* total)
     *total = tot;
     return off + x - v;
 }
+
+// Pixel of the current round taken by this thread (rounds cover 256
+// consecutive footprint pixels).  With `spread` the thread index is
+// bit-reversed: ray-table slots that sit next to each other (whose items run
+// on neighbouring lanes) then hold pixels far apart on the detector.  The
+// rays of adjacent pixels cross the same cells at the same steps, and LDS
+// atomics of one instruction from several lanes to one address serialise
+// (about 3x the cost of distinct addresses when 4 lanes share one).  The
+// interpolated adjoint gains about 20% from it; the Siddon adjoint (one
+// atomic per cell, items of whole cells) does not.
+template <bool spread>
+__device__ __forceinline__ int round_pixel(int p0)
+{
+    return p0 + (spread ? (int)(__builtin_bitreverse32(threadIdx.x) >> 24) : (int)threadIdx.x);
+}
+#ifndef CTMI_BWD_SPREAD
+#define CTMI_BWD_SPREAD 1
+#endif
+#ifndef CTMI_BWD_SID_SPREAD
+#define CTMI_BWD_SID_SPREAD 0
+#endif
 
 // Item -> ray map of one round: ray r owns items [pre[r], pre[r] + cnt).  The
 // first MAPCAP items are looked up in a byte table written by the rays
@@ -246,20 +271,22 @@ __device__ __forceinline__ float group_max(GroupLds& G, const float* __restrict_
 }
 
 // Add the view's fixed-point sums into the owned FP32 registers and clear
-// the integer accumulator (voxel (lx, ly, lz) of the brick sits at
-// ((lz + pad) * py + ly + pad) * px + lx + pad).
+// those cells (voxel (lx, ly, lz) of the brick sits at
+// ((lz + pad) * py + ly + pad) * px + lx + pad).  Each cell is read and
+// cleared by the same thread; cells outside the brick that no flush reads
+// are never cleared (they only collect discarded contributions).
 template <typename Acc>
-__device__ __forceinline__ void flush_view(Acc* acc, int n_acc, int px, int py, int pad, float inv, float own[OWN])
+__device__ __forceinline__ void flush_view(Acc* acc, int px, int py, int pad, float inv, float own[OWN])
 {
 #pragma unroll
     for (int m = 0; m < OWN; ++m) {
         const int i = threadIdx.x + 256 * m;
         const int lx = i % BX, ly = (i / BX) % BY, lz = i / (BX * BY);
-        const Acc a = acc[((lz + pad) * py + (ly + pad)) * px + (lx + pad)];
+        Acc* c = acc + ((lz + pad) * py + (ly + pad)) * px + (lx + pad);
+        const Acc a = *c;
+        *c = 0;
         own[m] = __builtin_fmaf((float)(long long)a, inv, own[m]);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_acc; i += blockDim.x) acc[i] = 0;
 }
 
 __device__ __forceinline__ void store_owned(float* __restrict__ vol, const float own[OWN], const VolDims& v, int x0,
@@ -275,25 +302,29 @@ __device__ __forceinline__ void store_owned(float* __restrict__ vol, const float
     }
 }
 
-// Accumulator cells.  64-bit: each contribution is an int32 against the
-// per-(brick, group) scale and the cells hold the group's exact sums.
-// 32-bit: the scale is chosen per round so that everything the round's rays
-// can add to one cell fits (cmax sum_r |y_r|, cmax the most one ray adds to
-// one cell per unit y), the cells are flushed after every round, and
-// contributions are rounded to nearest; 32-bit LDS atomics run about 1.4x
-// faster than 64-bit ones.
-#ifndef CTMI_BWD_ACC32
-#define CTMI_BWD_ACC32 1
-#endif
+// Accumulator cells.  Siddon: 64-bit cells; each contribution is an int32
+// against the per-(brick, group) scale and the cells hold the group's exact
+// sums (one atomic per segment).  Interpolated: 32-bit cells (LDS atomics
+// about 1.4x faster than 64-bit ones, and eight per sample); the scale is
+// chosen per round so that everything the round's rays can add to one cell
+// fits (cmax sum_r |y_r|, cmax the most one ray adds to one cell per unit
+// y), the cells are flushed after every round, and contributions are
+// rounded to nearest.
 #ifndef CTMI_BWD_SID_ACC32
 #define CTMI_BWD_SID_ACC32 0
 #endif
-constexpr bool ACC32 = CTMI_BWD_ACC32 != 0;
 constexpr bool SID_ACC32 = CTMI_BWD_SID_ACC32 != 0;
-typedef std::conditional<ACC32, int, u64>::type IAcc;
 typedef std::conditional<SID_ACC32, int, u64>::type SAcc;
 
-__device__ __forceinline__ void acc_add(int* a, float q) { atomicAdd(a, (int)__builtin_rintf(q)); }
+// floor(q + 1/2) as an int32 in one instruction (rintf costs a round and a
+// convert); it differs from round-half-even only on exact ties
+__device__ __forceinline__ int round_int(float q)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(q));
+    return r;
+}
+__device__ __forceinline__ void acc_add(int* a, float q) { atomicAdd(a, round_int(q)); }
 __device__ __forceinline__ void acc_add(u64* a, float q) { atomicAdd(a, to_fixed(q)); }
 
 constexpr int SID_CELLS = CTMI_BWD_SID_CELLS;   // dominant-axis cells per Siddon item
@@ -335,7 +366,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         float inv;
         float scale = SID_ACC32 ? 0.0f : fixed_scale(cmax, maxy, &inv);
         for (int p0 = 0; p0 < npx; p0 += 256) {
-            const int p = p0 + tid;
+            const int p = round_pixel<CTMI_BWD_SID_SPREAD != 0>(p0);
             int cnt = 0;
             float yr = 0.0f, yl_ = 0.0f;   // this ray's y, and y times its world length
             if (p < npx) {
@@ -463,12 +494,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             __syncthreads();
             if (SID_ACC32) {
                 // 32-bit cells hold one round's sums (bounded by the scale)
-                flush_view(acc, NB, BX, BY, 0, inv, own);
+                flush_view(acc, BX, BY, 0, inv, own);
                 __syncthreads();
             }
         }
         if (!SID_ACC32) {
-            flush_view(acc, NB, BX, BY, 0, inv, own);
+            flush_view(acc, BX, BY, 0, inv, own);
             __syncthreads();
         }
     }
@@ -509,10 +540,10 @@ __device__ __forceinline__ void halo_slot(int h, int& lx, int& ly, int& lz)
     }
 }
 
-// shell cells -> per-thread FP32 registers (accumulator origin at the brick
-// corner minus one voxel)
+// shell cells -> per-thread FP32 registers, clearing them (accumulator
+// origin at the brick corner minus one voxel)
 template <typename Acc>
-__device__ __forceinline__ void flush_shell(const Acc* acc, float inv, float hown[NH])
+__device__ __forceinline__ void flush_shell(Acc* acc, float inv, float hown[NH])
 {
 #pragma unroll
     for (int m = 0; m < NH; ++m) {
@@ -520,16 +551,52 @@ __device__ __forceinline__ void flush_shell(const Acc* acc, float inv, float how
         if (h < HALO_SLOTS) {
             int lx, ly, lz;
             halo_slot(h, lx, ly, lz);
-            const Acc a = acc[((lz + 1) * HY + (ly + 1)) * HX + (lx + 1)];
+            Acc* c = acc + ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);
+            const Acc a = *c;
+            *c = 0;
             hown[m] = __builtin_fmaf((float)(long long)a, inv, hown[m]);
         }
     }
 }
 
-#ifndef CTMI_BWD_HALO
-#define CTMI_BWD_HALO 1
-#endif
-constexpr bool HALO = CTMI_BWD_HALO != 0;
+// Rounds of the interpolated adjoint: RPT rays per thread, RAYS per round.
+// Ray-table slot s = tid + 256 h (h < RPT) holds footprint pixel
+// p0 + bitrev9(s), so slots next to each other (whose items run on
+// neighbouring lanes) hold pixels far apart on the detector.  Item -> slot
+// lookups go through a 16-bit map for the first IMAPCAP items of a round.
+constexpr int RPT = 2, RAYS = 256 * RPT;
+constexpr int IMAPCAP = 4096;
+static_assert(RAYS == 512, "slot permutation is a 9-bit reversal");
+
+__device__ __forceinline__ int slot_pixel(int s)
+{
+    return CTMI_BWD_SPREAD ? (int)(__builtin_bitreverse32((unsigned)s) >> 23) : s;
+}
+
+// Largest slot r in [0, RAYS) with pre[r] <= it (pre non-decreasing).
+__device__ __forceinline__ int owner_slot(const int* pre, int it)
+{
+    int lo = 0, hi = RAYS - 1;
+#pragma unroll
+    for (int st = 0; st < 9; ++st) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Inclusive scan of one int over a wave.
+__device__ __forceinline__ int wave_scan(int x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
@@ -538,16 +605,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                                                          float cmax, float* __restrict__ shell)
 {
     // accumulator over voxels [b0 - 1, b1] per axis, so every sample scatters
-    // to 8 fixed offsets without per-corner tests; the lower face holds
-    // corners outside the volume (discarded), the upper shell goes to the
-    // neighbours (or, without HALO, is discarded and the neighbours
-    // recompute those samples)
-    __shared__ IAcc acc[HX * HY * HZ];
+    // to 8 fixed offsets without per-corner tests; the lower face only
+    // receives corners outside the volume (first brick of an axis), the
+    // upper shell goes to the neighbours
+    __shared__ int acc[HX * HY * HZ];
     // ray table: (base, y) and (st, first sample | sample count << 16)
-    __shared__ float4 t_a[256], t_b[256];
-    __shared__ int t_pre[256];
-    __shared__ unsigned char imap[MAPCAP];
-    __shared__ int wsum[4];
+    __shared__ float4 t_a[RAYS], t_b[RAYS];
+    __shared__ int t_pre[RAYS];
+    __shared__ unsigned short imap[IMAPCAP];
+    __shared__ int wsum[RPT][4];
     __shared__ float wsumf[4];
     __shared__ GroupLds G;
     for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) acc[i] = 0;
@@ -560,101 +626,133 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     brick_origin(m, blockIdx.x, bx, by, bz);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
     const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
-    // HALO: the brick takes samples whose lower corner lies in [x0, x1) (from
-    // -1 for the first brick of an axis); otherwise every sample touching
-    // voxels [x0, x1), i.e. lower corner in [x0 - 1, x1).  Positions of those
-    // samples lie in [lo, hi) (voxel-centre coordinates).
-    const float lo[3] = {(HALO && x0 > 0) ? (float)x0 : x0 - 1.0f, (HALO && y0 > 0) ? (float)y0 : y0 - 1.0f,
-                         (HALO && z0 > 0) ? (float)z0 : z0 - 1.0f};
+    // the brick takes samples whose lower corner lies in [x0, x1) (from -1
+    // for the first brick of an axis); their positions lie in [lo, hi)
+    // (voxel-centre coordinates)
+    const float lo[3] = {x0 > 0 ? (float)x0 : -1.0f, y0 > 0 ? (float)y0 : -1.0f, z0 > 0 ? (float)z0 : -1.0f};
     const float hi[3] = {(float)x1, (float)y1, (float)z1};
     // a sample's lower corner (floor of its position) must lie in
     // [lo, hi - 1] per axis; the accumulator's byte offset of corner c is
-    // AB ((c_z - z0 + 1) HX HY + (c_y - y0 + 1) HX + (c_x - x0 + 1)), formed
+    // 4 ((c_z - z0 + 1) HX HY + (c_y - y0 + 1) HX + (c_x - x0 + 1)), formed
     // in FP32 (integers below 2^24)
     const float cmx = hi[0] - 1.0f, cmy = hi[1] - 1.0f, cmz = hi[2] - 1.0f;
-    constexpr float AB = (float)sizeof(IAcc);   // accumulator bytes per cell
+    constexpr float AB = (float)sizeof(int);   // accumulator bytes per cell
     const float aoff =
         -AB * ((float)(z0 - 1) * (float)(HX * HY) + (float)(y0 - 1) * (float)HX + (float)(x0 - 1));
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     char* const accb = reinterpret_cast<char*>(acc);
 
     for (int k = 0; k < nviews; k += GV) {
         const int ng = min(GV, nviews - k);
         __syncthreads();
         const int npx = make_group(G, tab, view0, k, ng, lo, hi, det);
-        if (npx == 0) continue;
-        // 64-bit cells: one scale per group from the largest |y| of its
-        // footprints; 32-bit cells: one scale per round (below)
-        const float maxy = ACC32 ? 1.0f : group_max(G, proj, det, k, npx);
-        if (!(maxy > 0.0f)) continue;
-        float inv;
-        float scale = ACC32 ? 0.0f : fixed_scale(cmax, maxy, &inv);
-        for (int p0 = 0; p0 < npx; p0 += 256) {
-            const int p = p0 + tid;
-            int cnt = 0;
-            float yr = 0.0f;   // this ray's y
-            if (p < npx) {
-                int gv, iu, iv;
-                group_pixel(G, p, gv, iu, iv);
-                const float* pk = proj + (int64_t)(k + gv) * det.nv * det.nu;
-                InterpRay ray;
-                if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, ray)) {
-                    // samples (relative to the anchor kc) inside the brick's box,
-                    // widened by 1e-3 of a sample against the reciprocal's
-                    // rounding (a sample outside the box adds nothing: its
-                    // weights are zeroed below)
-                    float kmin = -CTMI_INF, kmax = CTMI_INF;
-                    bool inside = true;
+        for (int p0 = 0; p0 < npx; p0 += RAYS) {
+            // --- ray setup: RPT rays per thread
+            int cnt[RPT];
+            float ya = 0.0f;   // sum of |y| over this thread's rays
+            float yr[RPT];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        if (ray.st[a] != 0.0f) {
-                            const float ia = __builtin_amdgcn_rcpf(ray.st[a]);
-                            const float ka = (lo[a] - ray.base[a]) * ia, kb = (hi[a] - ray.base[a]) * ia;
-                            kmin = fmaxf(kmin, fminf(ka, kb));
-                            kmax = fminf(kmax, fmaxf(ka, kb));
-                        } else {
-                            inside &= ray.base[a] > lo[a] && ray.base[a] < hi[a];
+            for (int h = 0; h < RPT; ++h) {
+                const int sl = tid + 256 * h;
+                const int p = p0 + slot_pixel(sl);
+                cnt[h] = 0;
+                yr[h] = 0.0f;
+                if (p < npx) {
+                    int gv, iu, iv;
+                    group_pixel(G, p, gv, iu, iv);
+                    InterpRay ray;
+                    if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, ray)) {
+                        // samples (relative to the anchor kc) inside the brick's
+                        // box, widened by 1e-3 of a sample against the
+                        // reciprocal's rounding (a sample outside the box adds
+                        // nothing: its weights are zeroed below)
+                        float kmin = -CTMI_INF, kmax = CTMI_INF;
+                        bool inside = true;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            if (ray.st[a] != 0.0f) {
+                                const float ia = __builtin_amdgcn_rcpf(ray.st[a]);
+                                const float ka = (lo[a] - ray.base[a]) * ia, kb = (hi[a] - ray.base[a]) * ia;
+                                kmin = fmaxf(kmin, fminf(ka, kb));
+                                kmax = fminf(kmax, fmaxf(ka, kb));
+                            } else {
+                                inside &= ray.base[a] > lo[a] && ray.base[a] < hi[a];
+                            }
                         }
-                    }
-                    if (inside && kmin < kmax + 2e-3f) {
-                        const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin - 1e-3f));
-                        const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax + 1e-3f));
-                        const int n = ke - ks + 1;
-                        if (n > 0 && n < 65536) {
-                            cnt = (n + INT_SAMPLES - 1) / INT_SAMPLES;
-                            // first sample relative to the anchor: |ks - kc| < 2^15
-                            // because a ray has fewer than 2^15 samples in the
-                            // volume (checked at plan creation)
-                            const int jn = ((ks - ray.kc) & 0xFFFF) | (n << 16);
-                            yr = pk[(int64_t)iv * det.nu + iu];
-                            t_a[tid] = make_float4(ray.base[0], ray.base[1], ray.base[2], 0.0f);
-                            t_b[tid] = make_float4(ray.st[0], ray.st[1], ray.st[2], __int_as_float(jn));
+                        if (inside && kmin < kmax + 2e-3f) {
+                            const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin - 1e-3f));
+                            const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax + 1e-3f));
+                            const int n = ke - ks + 1;
+                            if (n > 0 && n < 65536) {
+                                cnt[h] = (n + INT_SAMPLES - 1) / INT_SAMPLES;
+                                // first sample relative to the anchor: |ks - kc| < 2^15
+                                // because a ray has fewer than 2^15 samples in the
+                                // volume (checked at plan creation)
+                                const int jn = ((ks - ray.kc) & 0xFFFF) | (n << 16);
+                                const float* pk = proj + (int64_t)(k + gv) * det.nv * det.nu;
+                                yr[h] = pk[(int64_t)iv * det.nu + iu];
+                                ya += fabsf(yr[h]);
+                                t_a[sl] = make_float4(ray.base[0], ray.base[1], ray.base[2], 0.0f);
+                                t_b[sl] = make_float4(ray.st[0], ray.st[1], ray.st[2], __int_as_float(jn));
+                            }
                         }
                     }
                 }
             }
-            int total;
-            const int off = block_scan(cnt, wsum, &total);
-            if (ACC32) {
-                // one cell's round sum is at most cmax sum_r |y_r| (cmax: K
-                // samples of ds, K the most samples of one ray inside a
-                // 2x2x2-voxel support)
-                const float ysum = block_sum(cnt > 0 ? fabsf(yr) : 0.0f, wsumf);
-                if (!(ysum > 0.0f)) {
-                    __syncthreads();
-                    continue;
-                }
-                scale = fixed_scale(cmax, ysum, &inv);
+            // --- one block pass: item offsets (exclusive scan over slots in
+            // slot order) and the round's sum of |y| (fixed order)
+            int inc[RPT];
+#pragma unroll
+            for (int h = 0; h < RPT; ++h) inc[h] = wave_scan(cnt[h]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) ya += __shfl_xor(ya, o, 64);
+            if (lane == 63) {
+#pragma unroll
+                for (int h = 0; h < RPT; ++h) wsum[h][wid] = inc[h];
             }
-            if (cnt > 0) t_a[tid].w = yr * ds * scale;
-            t_pre[tid] = off;
+            if (lane == 0) wsumf[wid] = ya;
             __syncthreads();
-            fill_item_map(imap, off, cnt);
+            const float ysum = (wsumf[0] + wsumf[1]) + (wsumf[2] + wsumf[3]);
+            if (!(ysum > 0.0f)) {
+                // nothing to add: keep the LDS sums of this pass alive until
+                // every thread has read them
+                __syncthreads();
+                continue;
+            }
+            int base = 0, off[RPT];
+#pragma unroll
+            for (int h = 0; h < RPT; ++h) {
+                int before = 0, tot = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int t = wsum[h][w];
+                    before += w < wid ? t : 0;
+                    tot += t;
+                }
+                off[h] = base + before + inc[h] - cnt[h];
+                base += tot;
+            }
+            const int total = base;
+            // one cell's round sum is at most cmax sum_r |y_r| (cmax: K
+            // samples of ds, K the most samples of one ray inside a
+            // 2x2x2-voxel support)
+            float inv;
+            const float scale = fixed_scale(cmax, ysum, &inv);
+#pragma unroll
+            for (int h = 0; h < RPT; ++h) {
+                const int sl = tid + 256 * h;
+                t_pre[sl] = off[h];
+                if (cnt[h] > 0) {
+                    t_a[sl].w = yr[h] * ds * scale;
+                    const int e = min(off[h] + cnt[h], IMAPCAP);
+                    for (int i = off[h]; i < e; ++i) imap[i] = (unsigned short)sl;
+                }
+            }
             __syncthreads();
-            // items are taken round-robin: every lane runs at most
+            // --- items, taken round-robin: every lane runs at most
             // INT_SAMPLES samples per item, so the wave stays converged
             for (int it = tid; it < total; it += 256) {
-                const int r = it < MAPCAP ? (int)imap[it] : owner(t_pre, it);
+                const int r = it < IMAPCAP ? (int)imap[it] : owner_slot(t_pre, it);
                 const int q = it - t_pre[r];
                 const float4 ta = t_a[r], tb = t_b[r];
                 const int jn = __float_as_int(tb.w);
@@ -666,9 +764,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 // loop, so that the loop never waits on its own atomics
                 asm volatile("" ::"v"(bxr), "v"(byr), "v"(bzr), "v"(sxr), "v"(syr), "v"(szr), "v"(yv), "v"(j0),
                              "v"(cntq));
-                for (int qq = 0; qq < cntq; ++qq) {
+                // j runs over the item's samples as an exact FP32 integer
+                const float jend = (float)(j0 + cntq);
+                for (float j = (float)j0; j < jend; j += 1.0f) {
                     // same FP32 position as the forward kernel's sample k
-                    const float j = (float)(j0 + qq);
                     const float px = __builtin_fmaf(j, sxr, bxr);
                     const float py = __builtin_fmaf(j, syr, byr);
                     const float pz = __builtin_fmaf(j, szr, bzr);
@@ -683,44 +782,38 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                                                          __builtin_fmaf(cy, AB * (float)HX,
                                                                         __builtin_fmaf(cx, AB, aoff)));
                     const float ax_ = px - fx, ay_ = py - fy, az_ = pz - fz;
-                    const float yz1 = ok ? az_ * yv : 0.0f;
-                    const float yz0 = ok ? (1.0f - az_) * yv : 0.0f;
-                    const float w00 = (1.0f - ay_) * yz0, w10 = ay_ * yz0;
-                    const float w01 = (1.0f - ay_) * yz1, w11 = ay_ * yz1;
-                    const float bx0 = 1.0f - ax_;
-                    IAcc* a0 = reinterpret_cast<IAcc*>(accb + boff);
-                    acc_add(a0, bx0 * w00);
-                    acc_add(a0 + 1, ax_ * w00);
-                    acc_add(a0 + HX, bx0 * w10);
-                    acc_add(a0 + HX + 1, ax_ * w10);
-                    acc_add(a0 + HX * HY, bx0 * w01);
-                    acc_add(a0 + HX * HY + 1, ax_ * w01);
-                    acc_add(a0 + HX * HY + HX, bx0 * w11);
-                    acc_add(a0 + HX * HY + HX + 1, ax_ * w11);
+                    // trilinear weights times y, each pair split as (w - a w, a w)
+                    const float yo = ok ? yv : 0.0f;
+                    const float yz1 = az_ * yo, yz0 = yo - yz1;
+                    const float w10 = ay_ * yz0, w00 = yz0 - w10;
+                    const float w11 = ay_ * yz1, w01 = yz1 - w11;
+                    const float u00 = ax_ * w00, u10 = ax_ * w10, u01 = ax_ * w01, u11 = ax_ * w11;
+                    int* a0 = reinterpret_cast<int*>(accb + boff);
+                    acc_add(a0, w00 - u00);
+                    acc_add(a0 + 1, u00);
+                    acc_add(a0 + HX, w10 - u10);
+                    acc_add(a0 + HX + 1, u10);
+                    acc_add(a0 + HX * HY, w01 - u01);
+                    acc_add(a0 + HX * HY + 1, u01);
+                    acc_add(a0 + HX * HY + HX, w11 - u11);
+                    acc_add(a0 + HX * HY + HX + 1, u11);
                 }
             }
             __syncthreads();
-            if (ACC32) {
-                // 32-bit cells hold one round's sums (bounded by the scale)
-                if (HALO) flush_shell(acc, inv, hown);
-                flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
-                __syncthreads();
-            }
-        }
-        if (!ACC32) {
-            if (HALO) flush_shell(acc, inv, hown);
-            flush_view(acc, HX * HY * HZ, HX, HY, 1, inv, own);
-            __syncthreads();
+            // --- flush: 32-bit cells hold one round's sums (bounded by the
+            // scale).  No barrier is needed after it: the next round's
+            // atomics come after two more barriers, and nothing before them
+            // touches the accumulator.
+            flush_shell(acc, inv, hown);
+            flush_view(acc, HX, HY, 1, inv, own);
         }
     }
     store_owned(vol, own, v, x0, y0, z0, beta);
-    if (HALO) {
-        float* out = shell + (size_t)blockIdx.x * HALO_SLOTS;
+    float* out = shell + (size_t)blockIdx.x * HALO_SLOTS;
 #pragma unroll
-        for (int m2 = 0; m2 < NH; ++m2) {
-            const int h = threadIdx.x + 256 * m2;
-            if (h < HALO_SLOTS) out[h] = hown[m2];
-        }
+    for (int m2 = 0; m2 < NH; ++m2) {
+        const int h = threadIdx.x + 256 * m2;
+        if (h < HALO_SLOTS) out[h] = hown[m2];
     }
 }
 
@@ -780,9 +873,9 @@ hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, 
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.ds, ACC32 ? p.round_interp : p.entry_interp, p.d_halo);
+                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.round_interp, p.d_halo);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !HALO) return e;
+    if (e != hipSuccess) return e;
     const int64_t n = (int64_t)p.vol.nx * p.vol.ny * p.vol.nz;
     hipLaunchKernelGGL(k_halo_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vol, p.d_halo, p.vol, m);
     return hipGetLastError();

@@ -271,10 +271,9 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     p->det.nv = (int)geo->nDetector[0];
     p->det.nu = (int)geo->nDetector[1];
     p->ds = (float)(geo->accuracy * std::fmin(geo->dVoxel[0], std::fmin(geo->dVoxel[1], geo->dVoxel[2])));
-    // largest single contribution factors, which size the adjoints'
-    // fixed-point scale: one Siddon term is a chord of one cell (at most its
-    // diagonal); one interpolation term is a sample's tent weight (<= 1)
-    // times ds
+    // bounds that size the adjoints' fixed-point scales: one Siddon term is
+    // a chord of one cell (at most its diagonal); one interpolation term is
+    // a sample's tent weight (<= 1) times ds
     {
         double hdiag2 = 0.0;
         for (int a = 0; a < 3; ++a) hdiag2 += geo->dVoxel[a] * geo->dVoxel[a];
@@ -283,7 +282,6 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
         // one ray crosses a cell once, and items end on cell boundaries, so a
         // ray adds at most one chord to one cell
         p->round_siddon = (float)(hdiag * 1.0001);
-        p->entry_interp = (float)((double)p->ds * 1.0001);
         // samples of one ray inside a 2x2x2-voxel support: the chord is at most
         // 2 sqrt(3) voxel units and samples are at least ds / h_max apart
         // (one more for FP32 rounding of the positions)

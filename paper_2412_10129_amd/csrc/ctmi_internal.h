@@ -74,7 +74,6 @@ struct Plan {
     DetDims det;
     float ds;             // interpolated-projector step, mm
     float entry_siddon;   // largest single adjoint term factor, Siddon (one chord, mm)
-    float entry_interp;   // the same for the interpolated projector (ds, mm)
     float round_interp;   // most one ray adds to one adjoint cell per unit y: K ds (mm)
     float round_siddon;   // the same for Siddon: one chord (mm)
     float* d_halo;        // interpolated adjoint: CTMI_HALO_SLOTS floats per voxel brick
