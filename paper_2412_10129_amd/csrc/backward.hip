@@ -214,6 +214,7 @@ constexpr int GV = CTMI_BWD_GV;
 
 struct GroupLds {
     int u0[GV], v0[GV], w[GV], pre[GV + 1];
+    float rw[GV];   // 1 / w
     unsigned red;
 };
 
@@ -229,6 +230,7 @@ __device__ __forceinline__ int make_group(GroupLds& G, const ViewGeo* __restrict
         G.u0[g] = u0;
         G.v0[g] = v0;
         G.w[g] = ok ? u1 - u0 + 1 : 1;
+        G.rw[g] = 1.0f / (float)(ok ? u1 - u0 + 1 : 1);
         G.pre[g + 1] = ok ? (u1 - u0 + 1) * (v1 - v0 + 1) : 0;
     }
     if (threadIdx.x == 0) G.red = 0u;
@@ -241,16 +243,28 @@ __device__ __forceinline__ int make_group(GroupLds& G, const ViewGeo* __restrict
     return G.pre[GV];
 }
 
-// Candidate c of the group -> view g and pixel (iu, iv).
+// Candidate c of the group -> view g and pixel (iu, iv).  The row p / w is
+// estimated in FP32 (p / w <= nv <= 2^20, so the estimate is within 1/4 of
+// the quotient and its truncation off by at most one) and corrected with
+// the exact remainder (w <= nu <= 4096 and the row fit __umul24).
 __device__ __forceinline__ void group_pixel(const GroupLds& G, int c, int& g, int& iu, int& iv)
 {
     g = 0;
 #pragma unroll
     for (int i = 1; i < GV; ++i) g += c >= G.pre[i] ? 1 : 0;
     const int p = c - G.pre[g];
-    const int r = p / G.w[g];
+    const int w = G.w[g];
+    int r = (int)((float)p * G.rw[g]);
+    int rem = p - (int)__umul24((unsigned)r, (unsigned)w);
+    if (rem < 0) {
+        --r;
+        rem += w;
+    } else if (rem >= w) {
+        ++r;
+        rem -= w;
+    }
     iv = G.v0[g] + r;
-    iu = G.u0[g] + (p - r * G.w[g]);
+    iu = G.u0[g] + rem;
 }
 
 // Max |y| over the group's footprint pixels (block reduction).
@@ -425,7 +439,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             }
             if (cnt > 0) t_y[tid] = yl_ * scale;
             t_pre[tid] = off;
-            __syncthreads();
             fill_item_map(imap, off, cnt);
             __syncthreads();
             // items are taken round-robin (consecutive lanes on consecutive
@@ -641,6 +654,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         -AB * ((float)(z0 - 1) * (float)(HX * HY) + (float)(y0 - 1) * (float)HX + (float)(x0 - 1));
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     char* const accb = reinterpret_cast<char*>(acc);
+    const float inv_ds = 1.0f / ds;
 
     for (int k = 0; k < nviews; k += GV) {
         const int ng = min(GV, nviews - k);
@@ -661,7 +675,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     int gv, iu, iv;
                     group_pixel(G, p, gv, iu, iv);
                     InterpRay ray;
-                    if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, ray)) {
+                    if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, inv_ds, ray)) {
                         // samples (relative to the anchor kc) inside the brick's
                         // box, widened by 1e-3 of a sample against the
                         // reciprocal's rounding (a sample outside the box adds
@@ -671,7 +685,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             if (ray.st[a] != 0.0f) {
-                                const float ia = __builtin_amdgcn_rcpf(ray.st[a]);
+                                const float ia = ray.inv[a];
                                 const float ka = (lo[a] - ray.base[a]) * ia, kb = (hi[a] - ray.base[a]) * ia;
                                 kmin = fmaxf(kmin, fminf(ka, kb));
                                 kmax = fminf(kmax, fmaxf(ka, kb));

@@ -293,6 +293,7 @@ __device__ __forceinline__ void siddon_ray(const ViewGeo64& g, int iu, int iv, c
 struct InterpRay {
     float st[3];   // step per sample, voxel units
     float base[3]; // position of sample kc
+    float inv[3];  // rcp(st) where st != 0 (the clip's reciprocals, reusable)
     int kc, k0, k1;
 };
 
@@ -305,7 +306,7 @@ struct InterpRay {
 // projector and its transpose both call this function, so they visit the
 // same samples at the same FP32 positions.
 __device__ __forceinline__ bool interp_ray(const ViewGeo64& g, int iu, int iv, const VolDims& v, float ds,
-                                           InterpRay& r)
+                                           float inv_ds, InterpRay& r)
 {
     double S[3], d[3];
     pixel_ray64(g, iu, iv, S, d);
@@ -317,15 +318,20 @@ __device__ __forceinline__ bool interp_ray(const ViewGeo64& g, int iu, int iv, c
     rl = rl * __builtin_fma(-0.5 * L2, rl * rl, 1.5);
     const double sc = (double)ds * rl;
     const int n[3] = {v.nx, v.ny, v.nz};
-    float kmin = 0.0f, kmax = (float)(L2 * rl) / ds;
+    // samples up to the detector pixel (inv_ds = 1 / ds; a bound only:
+    // the volume's box below is tighter whenever the volume lies between
+    // source and detector)
+    float kmin = 0.0f, kmax = (float)(L2 * rl) * inv_ds;
     double Sc[3], st[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         Sc[a] = S[a] - 0.5;
         st[a] = d[a] * sc;
         const float stf = (float)st[a], Sf = (float)Sc[a];
+        r.inv[a] = 0.0f;
         if (stf != 0.0f) {
             const float inv = __builtin_amdgcn_rcpf(stf);
+            r.inv[a] = inv;
             const float ka = (-1.0f - Sf) * inv, kb = ((float)n[a] - Sf) * inv;
             kmin = fmaxf(kmin, fminf(ka, kb));
             kmax = fminf(kmax, fmaxf(ka, kb));

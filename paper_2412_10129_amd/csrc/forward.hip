@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(256) k_forward_interp(const float* __restrict_
     }
 
     InterpRay r;
-    const bool has = interp_ray(tab64[view0 + view], active ? iu : 0, active ? iv : 0, v, ds, r) && active;
+    const bool has = interp_ray(tab64[view0 + view], active ? iu : 0, active ? iv : 0, v, ds, 1.0f / ds, r) && active;
     int k = has ? r.k0 : 0;
     const int k1 = has ? r.k1 : -1;
     // sample k sits at base + (k - kc) st; along the dominant axis the slab
