@@ -351,6 +351,47 @@ def os_sart(geo: Geometry, angles, b, niter: int, blocksize: int, lam: float = 1
     return x
 
 
+def osem(geo: Geometry, angles, b, niter: int, blocksize: Optional[int] = None, kind: str = "interp", x0=None):
+    """MLEM and its ordered-subsets form OSEM (section 2.2, the MLEM update
+    for the Kullback-Leibler data term; its OS counterpart, section 2.2.2).
+
+    The printed update divides x by "A 1"; a volume can only be divided by
+    the volume-sized column sums, so the normaliser is read as the
+    sensitivity A^T 1 (the Shepp-Vardi update).  Per block s (MLEM: one block
+    of all views):
+        x <- x / (A_s^T 1) * A_s^T (b_s / (A_s x))
+    with the ratio set to 0 where (A_s x)_i <= 0 and x set to 0 where
+    (A_s^T 1)_j = 0.  Start x0 = 1 (EM needs a positive start).  One
+    iteration is one pass over all blocks.
+    """
+    angles = _f64(angles)
+    b = _f64(b)
+    nv = len(angles)
+    x = np.ones(geo.nVoxel) if x0 is None else _f64(x0).copy()
+    blocks = subsets(nv, nv if blocksize is None else blocksize)
+    sens = [backward(geo, angles[idx], np.ones((len(idx),) + tuple(geo.nDetector)), kind) for idx in blocks]
+    for _ in range(niter):
+        for s, idx in enumerate(blocks):
+            a = angles[idx]
+            ax = forward(geo, a, x, kind)
+            ratio = np.zeros_like(ax)
+            pos = ax > 0
+            ratio[pos] = b[idx][pos] / ax[pos]
+            bp = backward(geo, a, ratio, kind)
+            x = x * _recip0(sens[s]) * bp
+    return x
+
+
+def poisson_loglik(geo: Geometry, angles, b, x, kind: str = "interp") -> float:
+    """Poisson log-likelihood (up to a constant) of data b for image x:
+    sum_i b_i log (A x)_i - (A x)_i over rays with (A x)_i > 0 (the quantity
+    EM increases)."""
+    ax = forward(geo, _f64(angles), _f64(x), kind)
+    b = _f64(b)
+    pos = ax > 0
+    return float(np.sum(b[pos] * np.log(ax[pos])) - np.sum(ax))
+
+
 # --------------------------------------------------------------- metrics
 def fov_mask(geo: Geometry) -> np.ndarray:
     """Voxels whose centre lies inside the volume's inscribed cylinder."""

@@ -473,6 +473,68 @@ def test_sirt_one_block_one_pass_is_weighted_gradient_step(orc):
     assert _rel(got.ravel(), want) < 1e-12
 
 
+# ------------------------------------------------------------ MLEM / OSEM
+_EMGEO = Geometry(DSD=60.0, DSO=40.0, nVoxel=(6, 6, 6), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 8),
+                  dDetector=(1.4, 1.4))
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_mlem_preserves_counts(orc, kind):
+    """After one EM update the model's total counts equal the data's over
+    the rays the model reaches: sum_i (A x1)_i = sum_{i: (A x0)_i > 0} b_i
+    (the sensitivity normalisation cancels; a dropped or misplaced
+    normaliser breaks it)."""
+    geo, ang = _EMGEO, synth.circular_angles(10)
+    rng = np.random.Generator(np.random.PCG64(46))
+    x0 = 0.5 + rng.random(geo.nVoxel)
+    b = rng.random((10,) + geo.nDetector) * 3.0
+    x1 = orc.osem(geo, ang, b, 1, x0=x0, kind=kind)
+    ax0 = orc.forward(geo, ang, x0, kind)
+    want = float(b[ax0 > 0].sum())
+    got = float(orc.forward(geo, ang, x1, kind).sum())
+    assert abs(got - want) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("blocksize", [None, 3])
+def test_mlem_osem_fixed_point_on_consistent_data(orc, blocksize):
+    """With b = A x_t and x_t > 0, x_t is a fixed point of MLEM and OSEM."""
+    geo, ang = _EMGEO, synth.circular_angles(12)
+    xt = 0.2 + np.random.Generator(np.random.PCG64(47)).random(geo.nVoxel)
+    b = orc.forward(geo, ang, xt, "interp")
+    x = orc.osem(geo, ang, b, 1, blocksize=blocksize, x0=xt, kind="interp")
+    # voxels no ray reaches are set to 0 by the update
+    seen = orc.backward(geo, ang, np.ones((12,) + geo.nDetector), "interp") > 0
+    assert _rel(x[seen], xt[seen]) < 1e-12
+    assert np.all(x[~seen] == 0.0)
+
+
+def test_mlem_loglik_increases_and_stays_positive(orc):
+    """EM never decreases the Poisson log-likelihood (Dempster-Laird-Rubin;
+    Shepp-Vardi for emission/transmission counts) and keeps x >= 0."""
+    geo, ang = _EMGEO, synth.circular_angles(10)
+    rng = np.random.Generator(np.random.PCG64(48))
+    xt = rng.random(geo.nVoxel)
+    b = rng.poisson(20.0 * orc.forward(geo, ang, xt, "siddon")) / 20.0
+    x = None
+    ll = []
+    for _ in range(8):
+        x = orc.osem(geo, ang, b, 1, x0=x, kind="siddon")
+        assert np.all(x >= 0.0)
+        ll.append(orc.poisson_loglik(geo, ang, b, x, "siddon"))
+    assert all(ll[i + 1] >= ll[i] - 1e-9 * abs(ll[i]) for i in range(len(ll) - 1)), ll
+    assert ll[-1] > ll[0]
+
+
+def test_osem_one_block_equals_mlem_and_blocks_differ(orc):
+    geo, ang = _EMGEO, synth.circular_angles(12)
+    b = np.random.Generator(np.random.PCG64(49)).random((12,) + geo.nDetector)
+    m = orc.osem(geo, ang, b, 2, kind="interp")
+    o = orc.osem(geo, ang, b, 2, blocksize=12, kind="interp")
+    assert _rel(o, m) < 1e-14
+    o4 = orc.osem(geo, ang, b, 2, blocksize=4, kind="interp")
+    assert _rel(o4, m) > 1e-3
+
+
 # ------------------------------------------------------------------ PSNR
 def test_psnr_closed_form():
     import oracle
