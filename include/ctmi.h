@@ -188,6 +188,19 @@ int ctmi_sart_residual(const float* b, const float* ax, const float* w, float* o
 int ctmi_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg,
                      void* stream);
 
+/* MLEM / OSEM ratio (section 2.2, the update for the Kullback-Leibler data
+ * term, and its ordered-subsets form, section 2.2.2): out = b / ax where
+ * ax > 0, else 0.  b, ax, out: n device floats (projections of one block);
+ * out may alias ax.  Errors: CTMI_EINVAL for NULL or misaligned pointers or
+ * n < 0. */
+int ctmi_em_ratio(const float* b, const float* ax, float* out, int64_t n, void* stream);
+
+/* MLEM / OSEM multiplicative update: x = x * v * bp, with v = 1 / (A_s^T 1)
+ * (ctmi_recip_or_zero of the block's sensitivity; 0 where no ray reaches)
+ * and bp = A_s^T (ratio).  x, v, bp: n device floats (volumes); x is
+ * updated in place.  Errors as ctmi_em_ratio. */
+int ctmi_em_update(float* x, const float* v, const float* bp, int64_t n, void* stream);
+
 /* Squared error inside the field of view (section 2.2.3 ground-truth error
  * history): out[0] = sum (x - gt)^2 and out[1] = voxel count, over voxels
  * whose centre lies inside the volume's inscribed cylinder, FP64.

@@ -61,6 +61,8 @@ _SIGS = {
     "ctmi_recip_or_zero": (c_int, [c_p, c_p, c_i64, c_p]),
     "ctmi_sart_residual": (c_int, [c_p, c_p, c_p, c_p, c_i64, c_p]),
     "ctmi_sart_update": (c_int, [c_p, c_p, c_p, c_i64, c_f, c_int, c_p]),
+    "ctmi_em_ratio": (c_int, [c_p, c_p, c_p, c_i64, c_p]),
+    "ctmi_em_update": (c_int, [c_p, c_p, c_p, c_i64, c_p]),
     "ctmi_fov_sq_err": (c_int, [c_p, c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
     # learned prior (ctmi_unet.h)
     "ctmi_conv3d_bf16_fwd": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_int, c_p, c_p, c_int, c_int, c_p,

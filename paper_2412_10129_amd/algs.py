@@ -143,6 +143,56 @@ def os_sart(plan: Plan, b: torch.Tensor, niter: int, blocksize: int, lam: float 
     return OSSART(plan, blocksize, kind).run(b, niter, lam, nonneg, x0)
 
 
+class OSEM:
+    """MLEM and OSEM (section 2.2, the update for the Kullback-Leibler data
+    term; its ordered-subsets counterpart, section 2.2.2).  The update's
+    normaliser is the sensitivity A_s^T 1 (a volume):
+        x <- x * (1 / A_s^T 1) * A_s^T (b_s / A_s x)
+    with the ratio 0 where A_s x <= 0 and x 0 where no ray of the block
+    reaches the voxel.  MLEM is one block of all views.  Precomputes
+    V_s = 1 / (A_s^T 1) per block (one volume per block)."""
+
+    def __init__(self, plan: Plan, blocksize: Optional[int] = None, kind: str = "interp"):
+        self.plan, self.kind = plan, kind
+        self.blocks = subsets(plan.nviews, plan.nviews if blocksize is None else blocksize)
+        dev = plan.device
+        self.V = []
+        for v0, nb in self.blocks:
+            ones_p = torch.ones(plan.proj_shape(nb), dtype=torch.float32, device=dev)
+            self.V.append(ops.recip_or_zero(plan.backproject(ones_p, kind=kind, view0=v0, nviews=nb)))
+        mb = max(nb for _, nb in self.blocks)
+        self._e = torch.empty(plan.proj_shape(mb), dtype=torch.float32, device=dev)
+        self._bp = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+
+    def step(self, x: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        """One iteration (one pass over all blocks), in place on x."""
+        plan = self.plan
+        for s, (v0, nb) in enumerate(self.blocks):
+            e = self._e[:nb]
+            plan.forward(x, out=e, kind=self.kind, view0=v0, nviews=nb)
+            ops.em_ratio(b[v0:v0 + nb], e, e)
+            plan.backproject(e, out=self._bp, kind=self.kind, view0=v0, nviews=nb)
+            ops.em_update(x, self.V[s], self._bp)
+        return x
+
+    def run(self, b: torch.Tensor, niter: int, x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        plan = self.plan
+        x = torch.ones(plan.vol_shape, dtype=torch.float32, device=plan.device) if x0 is None else x0.clone()
+        for _ in range(niter):
+            self.step(x, b)
+        return x
+
+
+def mlem(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp",
+         x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+    return OSEM(plan, None, kind).run(b, niter, x0)
+
+
+def osem(plan: Plan, b: torch.Tensor, niter: int, blocksize: int, kind: str = "interp",
+         x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+    return OSEM(plan, blocksize, kind).run(b, niter, x0)
+
+
 def pnp_cgls(plan: Plan, b: torch.Tensor, niter: int, denoiser, every: int = 5, ratio: float = 1.05,
              kind: str = "interp", x_gt: Optional[torch.Tensor] = None, data_range: Optional[float] = None,
              timing: bool = False):

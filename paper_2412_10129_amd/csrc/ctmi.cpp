@@ -495,6 +495,24 @@ int ctmi_sart_update(float* x, const float* v, const float* bp, int64_t n, float
                     "sart_update");
 }
 
+int ctmi_em_ratio(const float* b, const float* ax, float* out, int64_t n, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(b, "b")) || (rc = check_ptr(ax, "ax")) || (rc = check_ptr(out, "out")))
+        return rc;
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_em_ratio(b, ax, out, n, static_cast<hipStream_t>(stream)), "em_ratio");
+}
+
+int ctmi_em_update(float* x, const float* v, const float* bp, int64_t n, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(x, "x")) || (rc = check_ptr(v, "v")) || (rc = check_ptr(bp, "bp")))
+        return rc;
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_em_update(x, v, bp, n, static_cast<hipStream_t>(stream)), "em_update");
+}
+
 int ctmi_fov_sq_err(const ctmi_plan* plan, const float* x, const float* gt, double* out, void* ws, size_t ws_bytes,
                     void* stream)
 {

@@ -105,6 +105,8 @@ hipError_t launch_sart_residual(const float* b, const float* ax, const float* w,
                                 hipStream_t s);
 hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg,
                               hipStream_t s);
+hipError_t launch_em_ratio(const float* b, const float* ax, float* out, int64_t n, hipStream_t s);
+hipError_t launch_em_update(float* x, const float* v, const float* bp, int64_t n, hipStream_t s);
 hipError_t launch_fov_sq_err(const Plan& p, const float* x, const float* gt, double* out, double* ws,
                              hipStream_t s);
 

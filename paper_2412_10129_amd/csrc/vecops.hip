@@ -123,6 +123,24 @@ __global__ void __launch_bounds__(256) k_sart_update(float* __restrict__ x, cons
     }
 }
 
+// EM ratio (MLEM/OSEM, section 2.2): out = b / ax where ax > 0, else 0.
+__global__ void __launch_bounds__(256) k_em_ratio(const float* __restrict__ b, const float* ax, float* out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float a = ax[i];
+        out[i] = a > 0.0f ? b[i] / a : 0.0f;
+    }
+}
+
+// EM update: x = x * v * bp, v = 1 / (A^T 1) (0 where no ray reaches).
+__global__ void __launch_bounds__(256) k_em_update(float* __restrict__ x, const float* __restrict__ v,
+                                                   const float* __restrict__ bp, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = x[i] * v[i] * bp[i];
+}
+
 __global__ void __launch_bounds__(RB) k_fov_partial(const float* __restrict__ x, const float* __restrict__ gt,
                                                     VolDims v, float cx, float cy, float r2,
                                                     double* __restrict__ part)
@@ -213,6 +231,18 @@ hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t
                               hipStream_t s)
 {
     hipLaunchKernelGGL(k_sart_update, dim3(stream_blocks(n)), dim3(256), 0, s, x, v, bp, n, lam, nonneg);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_ratio(const float* b, const float* ax, float* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_em_ratio, dim3(stream_blocks(n)), dim3(256), 0, s, b, ax, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_em_update(float* x, const float* v, const float* bp, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_em_update, dim3(stream_blocks(n)), dim3(256), 0, s, x, v, bp, n);
     return hipGetLastError();
 }
 

@@ -185,3 +185,17 @@ def sart_update(x, v, bp, lam=1.0, nonneg=True, stream=None):
     L.check(L.lib().ctmi_sart_update(_ptr(x, "x"), _ptr(v, "v", n), _ptr(bp, "bp", n), n, float(lam),
                                      1 if nonneg else 0, _stream(stream)))
     return x
+
+
+def em_ratio(b, ax, out, stream=None):
+    """out = b / ax where ax > 0, else 0 (MLEM/OSEM ratio)."""
+    n = b.numel()
+    L.check(L.lib().ctmi_em_ratio(_ptr(b, "b"), _ptr(ax, "ax", n), _ptr(out, "out", n), n, _stream(stream)))
+    return out
+
+
+def em_update(x, v, bp, stream=None):
+    """x = x * v * bp (MLEM/OSEM update, v = 1 / (A^T 1))."""
+    n = x.numel()
+    L.check(L.lib().ctmi_em_update(_ptr(x, "x"), _ptr(v, "v", n), _ptr(bp, "bp", n), n, _stream(stream)))
+    return x

@@ -217,6 +217,52 @@ def test_os_sart_matches_oracle(P, orc, blocksize, nonneg):
     assert _rel(got, want) < 1e-4, _rel(got, want)
 
 
+@pytest.mark.parametrize("blocksize", [None, 6])
+def test_mlem_osem_matches_oracle(P, orc, blocksize):
+    """MLEM (one block) and OSEM (blocks of 6 views), 3 iterations from
+    x0 = 1, against the FP64 oracle.  Each iteration applies A and A^T (each
+    within 1e-4 of the oracle) and multiplies the ratio into x, so relative
+    errors add over the 3 iterations: bar 1e-3, as for CGLS-20."""
+    geo = Geometry(DSD=400.0, DSO=250.0, nVoxel=(20, 24, 28), dVoxel=(1.0, 1.0, 1.0), nDetector=(30, 40),
+                   dDetector=(1.3, 1.3))
+    ang = synth.circular_angles(24)
+    x_gt = synth.uniform_volume(geo, 19)
+    rng = np.random.Generator(np.random.PCG64(20))
+    b = rng.poisson(50.0 * orc.forward(geo, ang, x_gt, "interp")) / 50.0
+    b = b.astype(np.float32)
+    plan = P.Plan(geo, ang)
+    if blocksize is None:
+        got = _host(P.mlem(plan, _dev(b), 3, kind="interp"))
+    else:
+        got = _host(P.osem(plan, _dev(b), 3, blocksize, kind="interp"))
+    want = orc.osem(geo, ang, b.astype(np.float64), 3, blocksize=blocksize, kind="interp")
+    assert np.all(got >= 0.0)
+    assert _rel(got, want) < 1e-3, _rel(got, want)
+
+
+def test_em_elementwise_kernels_bit_exact(P):
+    """The EM ratio and update are single IEEE FP32 operations per element:
+    equal bit for bit to numpy's FP32 arithmetic, guards included (ax <= 0
+    gives 0; v = 0 gives 0)."""
+    from paper_2412_10129_amd import ops
+    rng = np.random.Generator(np.random.PCG64(21))
+    n = 100003
+    b = rng.random(n).astype(np.float32) * 5
+    ax = (rng.random(n).astype(np.float32) - 0.1)
+    ax[::97] = 0.0
+    want = np.where(ax > 0, b / np.where(ax > 0, ax, 1), 0).astype(np.float32)
+    out = _dev(np.zeros(n, np.float32))
+    got = _host(ops.em_ratio(_dev(b), _dev(ax), out))
+    assert np.array_equal(got, want)
+    x = rng.random(n).astype(np.float32)
+    v = rng.random(n).astype(np.float32)
+    v[::89] = 0.0
+    bp = rng.random(n).astype(np.float32) * 3
+    xd = _dev(x)
+    ops.em_update(xd, _dev(v), _dev(bp))
+    assert np.array_equal(_host(xd), (x * v) * bp)
+
+
 @pytest.mark.parametrize("kind", ["siddon", "interp"])
 def test_backproject_heavy_tailed_projections(P, orc, kind):
     """A^T of projections whose values span four decades (one pixel in a
