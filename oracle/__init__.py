@@ -392,6 +392,114 @@ def poisson_loglik(geo: Geometry, angles, b, x, kind: str = "interp") -> float:
     return float(np.sum(b[pos] * np.log(ax[pos])) - np.sum(ax))
 
 
+# ----------------------------------------------------- TV and ASD-POCS
+def _tv_terms(x, delta: float, wref=None):
+    """Backward differences d_a(u) = x_u - x_{u - e_a} (axes z, y, x) at
+    every voxel u whose three backward neighbours exist, and the adaptive
+    weights w_a = exp(-(d_a / delta)^2) of the adaptive-weighted TV of
+    section 2.2.3 (from wref's differences; w = 1 for delta = inf)."""
+    x = _f64(x)
+    c = x[1:, 1:, 1:]
+    d = [c - x[:-1, 1:, 1:], c - x[1:, :-1, 1:], c - x[1:, 1:, :-1]]
+    if wref is None:
+        dw = d
+    else:
+        r = _f64(wref)
+        cr = r[1:, 1:, 1:]
+        dw = [cr - r[:-1, 1:, 1:], cr - r[1:, :-1, 1:], cr - r[1:, 1:, :-1]]
+    if math.isinf(delta):
+        w = [np.ones_like(c)] * 3
+    else:
+        w = [np.exp(-(a / delta) ** 2) for a in dw]
+    return d, w
+
+
+def awtv(x, delta: float = math.inf, eps: float = 0.0, wref=None) -> float:
+    """Adaptive-weighted total variation (section 2.2.3, written there in
+    2-D; here with the third axis added the same way):
+        sum_u sqrt(w_z d_z^2 + w_y d_y^2 + w_x d_x^2 + eps)
+    over voxels u with all three backward neighbours; plain (isotropic) TV
+    for delta = inf.  eps > 0 smooths the norm at zero differences.  The
+    weights are taken from wref's differences when given (x otherwise)."""
+    d, w = _tv_terms(x, delta, wref)
+    return float(np.sum(np.sqrt(w[0] * d[0] ** 2 + w[1] * d[1] ** 2 + w[2] * d[2] ** 2 + eps)))
+
+
+def awtv_grad(x, delta: float = math.inf, eps: float = 1e-8):
+    """Gradient of awtv with the weights held at their values for x (the
+    adaptive weights are lagged: recomputed from the current image before
+    each descent step, not differentiated).  Term u contributes
+    w_a d_a / s_u to voxel u and -w_a d_a / s_u to u - e_a, with
+    s_u = sqrt(sum_a w_a d_a^2 + eps); a term with s_u = 0 contributes 0."""
+    x = _f64(x)
+    d, w = _tv_terms(x, delta)
+    s2 = w[0] * d[0] ** 2 + w[1] * d[1] ** 2 + w[2] * d[2] ** 2 + eps
+    s = np.sqrt(s2)
+    inv = np.zeros_like(s)
+    inv[s > 0] = 1.0 / s[s > 0]
+    q = [w[a] * d[a] * inv for a in range(3)]
+    g = np.zeros_like(x)
+    g[1:, 1:, 1:] += q[0] + q[1] + q[2]
+    g[:-1, 1:, 1:] -= q[0]
+    g[1:, :-1, 1:] -= q[1]
+    g[1:, 1:, :-1] -= q[2]
+    return g
+
+
+def asd_pocs(geo: Geometry, angles, b, niter: int, blocksize: int = 1, kind: str = "interp", lam: float = 1.0,
+             lam_red: float = 0.99, alpha: float = 0.002, alpha_red: float = 0.95, ng: int = 20,
+             rmax: float = 0.95, eps_data: float = 0.0, delta: float = math.inf, eps_tv: float = 1e-8,
+             nonneg: bool = True, x0=None):
+    """ASD-POCS and OS-ASD-POCS (the POCS class of section 2.2: a data
+    step alternated with adaptive TV steepest descent, after Sidky and Pan;
+    OS version with blocks of views, section 2.2.2; AwTV for finite delta,
+    section 2.2.3).  Per iteration:
+      1. data step: one OS-SART pass (blocks of `blocksize` views, step lam,
+         x = max(x, 0) after each block if nonneg);
+      2. dd = |A x - b|, dp = |x - x_before_data_step|;
+         on the first iteration the TV step length is dtvg = alpha dp;
+      3. ng steps x <- x - dtvg g / |g|, g = awtv_grad(x) (skipped when
+         |g| = 0);
+      4. dg = |x - x_before_tv|; if dg > rmax dp and dd > eps_data then
+         dtvg <- dtvg alpha_red;
+      5. lam <- lam lam_red.
+    The paper names the algorithm and its parameters without the steps;
+    these follow Sidky and Pan's published description."""
+    angles = _f64(angles)
+    b = _f64(b)
+    x = np.zeros(geo.nVoxel) if x0 is None else _f64(x0).copy()
+    blocks = subsets(len(angles), blocksize)
+    W, V = [], []
+    for idx in blocks:
+        a = angles[idx]
+        W.append(_recip0(forward(geo, a, np.ones(geo.nVoxel), kind)))
+        V.append(_recip0(backward(geo, a, np.ones((len(idx),) + tuple(geo.nDetector)), kind)))
+    dtvg = None
+    for k in range(niter):
+        x_prev = x.copy()
+        for s, idx in enumerate(blocks):
+            a = angles[idx]
+            e = b[idx] - forward(geo, a, x, kind)
+            x = x + lam * V[s] * backward(geo, a, W[s] * e, kind)
+            if nonneg:
+                x = np.maximum(x, 0.0)
+        dd = float(np.linalg.norm(forward(geo, angles, x, kind) - b))
+        dp = float(np.linalg.norm(x - x_prev))
+        if dtvg is None:
+            dtvg = alpha * dp
+        x_tv = x.copy()
+        for _ in range(ng):
+            g = awtv_grad(x, delta, eps_tv)
+            gn = float(np.linalg.norm(g))
+            if gn > 0:
+                x = x - dtvg * g / gn
+        dg = float(np.linalg.norm(x - x_tv))
+        if dg > rmax * dp and dd > eps_data:
+            dtvg *= alpha_red
+        lam *= lam_red
+    return x
+
+
 # --------------------------------------------------------------- metrics
 def fov_mask(geo: Geometry) -> np.ndarray:
     """Voxels whose centre lies inside the volume's inscribed cylinder."""

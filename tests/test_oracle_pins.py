@@ -535,6 +535,86 @@ def test_osem_one_block_equals_mlem_and_blocks_differ(orc):
     assert _rel(o4, m) > 1e-3
 
 
+# ------------------------------------------------------- TV / ASD-POCS
+def test_tv_of_voxel_aligned_cube_closed_form(orc):
+    """Isotropic TV (backward differences, eps = 0) of a cube of side m and
+    height h in a zero background: the three upper faces give h per face
+    voxel (3 m^2), the lower faces h per voxel on one face (3 (m-1)^2),
+    sqrt(2) h on an edge (3 (m-1)) and sqrt(3) h at the corner."""
+    m, h = 5, 1.5
+    x = np.zeros((12, 13, 11))
+    x[3:3 + m, 4:4 + m, 2:2 + m] = h
+    want = h * (3 * m * m + 3 * (m - 1) ** 2 + 3 * math.sqrt(2) * (m - 1) + math.sqrt(3))
+    assert abs(orc.awtv(x) - want) < 1e-12 * want
+
+
+def test_awtv_limits(orc):
+    """delta -> inf gives plain TV; delta far below the cube's jump switches
+    its edges off (weights exp(-(h/delta)^2))."""
+    x = np.zeros((10, 10, 10))
+    x[2:7, 3:8, 2:6] = 2.0
+    assert abs(orc.awtv(x, delta=1e9) - orc.awtv(x)) < 1e-12 * orc.awtv(x)
+    assert orc.awtv(x, delta=0.1) < 1e-80
+
+
+@pytest.mark.parametrize("delta", [math.inf, 0.35])
+def test_awtv_gradient_matches_finite_differences(orc, delta):
+    """Central differences of sum sqrt(sum_a w_a d_a(y)^2 + eps) at y = x,
+    the weights held at x's values, equal awtv_grad(x) (a dropped
+    neighbour term, a wrong sign or index fails this)."""
+    rng = np.random.Generator(np.random.PCG64(50))
+    x = rng.random((5, 6, 7))
+    eps = 1e-6
+    g = orc.awtv_grad(x, delta, eps)
+    fd = np.zeros_like(x)
+    hstep = 1e-6
+    for i in np.ndindex(x.shape):
+        xp = x.copy(); xp[i] += hstep
+        xm = x.copy(); xm[i] -= hstep
+        fd[i] = (orc.awtv(xp, delta, eps, wref=x) - orc.awtv(xm, delta, eps, wref=x)) / (2 * hstep)
+    assert _rel(g, fd) < 1e-7
+
+
+def test_tv_steepest_descent_step_reduces_tv(orc):
+    rng = np.random.Generator(np.random.PCG64(51))
+    x = rng.random((8, 8, 8))
+    g = orc.awtv_grad(x, eps=1e-8)
+    x1 = x - 1e-3 * g / np.linalg.norm(g)
+    assert orc.awtv(x1, eps=1e-8) < orc.awtv(x, eps=1e-8)
+
+
+@pytest.mark.parametrize("blocksize", [1, 4])
+def test_asd_pocs_without_tv_steps_is_os_sart_with_decaying_step(orc, blocksize):
+    """With no TV steps (ng = 0) ASD-POCS is OS-SART whose step shrinks by
+    lam_red every pass."""
+    geo = _EMGEO
+    ang = synth.circular_angles(8)
+    rng = np.random.Generator(np.random.PCG64(52))
+    b = orc.forward(geo, ang, rng.random(geo.nVoxel), "interp")
+    got = orc.asd_pocs(geo, ang, b, 3, blocksize=blocksize, ng=0, lam=0.9, lam_red=0.8, kind="interp")
+    x = None
+    lam = 0.9
+    for _ in range(3):
+        x = orc.os_sart(geo, ang, b, 1, blocksize, lam=lam, nonneg=True, kind="interp", x0=x)
+        lam *= 0.8
+    assert _rel(got, x) < 1e-13
+
+
+def test_asd_pocs_beats_os_sart_on_sparse_piecewise_constant(orc):
+    """On a piecewise-constant phantom from 6 views, the TV steps lower the
+    error of the same number of data passes."""
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(10, 10, 10), dVoxel=(1.0, 1.0, 1.0), nDetector=(12, 12),
+                   dDetector=(1.4, 1.4))
+    ang = synth.circular_angles(6)
+    xt = np.zeros(geo.nVoxel)
+    xt[2:8, 3:7, 2:8] = 1.0
+    xt[4:6, 4:6, 4:6] = 2.0
+    b = orc.forward(geo, ang, xt, "interp")
+    xs = orc.os_sart(geo, ang, b, 10, 1, kind="interp")
+    xa = orc.asd_pocs(geo, ang, b, 10, blocksize=1, kind="interp")
+    assert np.linalg.norm(xa - xt) < np.linalg.norm(xs - xt)
+
+
 # ------------------------------------------------------------------ PSNR
 def test_psnr_closed_form():
     import oracle
