@@ -188,6 +188,26 @@ int ctmi_sart_residual(const float* b, const float* ax, const float* w, float* o
 int ctmi_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg,
                      void* stream);
 
+/* Gradient of the adaptive-weighted total variation (section 2.2.3, the
+ * AwTV norm, written there in 2-D; here with the z axis added the same way)
+ * of a volume x[nz][ny][nx] (x fastest), into g (same layout; must not alias
+ * x).  With backward differences d_a(u) = x_u - x_{u - e_a} at every voxel u
+ * whose three backward neighbours exist, weights w_a = exp(-(d_a/delta)^2)
+ * (plain isotropic TV when delta <= 0 or infinite) and
+ * s_u = sqrt(sum_a w_a d_a^2 + eps):
+ *     g_v = sum_a w_a(v) d_a(v) / s_v - sum_a w_a(v+e_a) d_a(v+e_a) / s_{v+e_a}
+ * (terms with s = 0 contribute 0; the weights are held at their current
+ * values, not differentiated).  Used by the TV steps of ASD-POCS.  Errors:
+ * CTMI_EINVAL (NULL/misaligned pointers, aliasing, dims < 1, NaN delta,
+ * eps < 0), CTMI_EOVERFLOW (2^31 voxels or more). */
+int ctmi_awtv_grad(const float* x, float* g, int64_t nz, int64_t ny, int64_t nx, float delta, float eps,
+                   void* stream);
+
+/* TV steepest-descent step of ASD-POCS: x -= step * g / sqrt(*gnorm2), with
+ * gnorm2 a device double (e.g. ctmi_dot(g, g)); no change when *gnorm2 is
+ * 0.  x, g: n device floats. */
+int ctmi_tv_step(float* x, const float* g, int64_t n, const double* gnorm2, float step, void* stream);
+
 /* MLEM / OSEM ratio (section 2.2, the update for the Kullback-Leibler data
  * term, and its ordered-subsets form, section 2.2.2): out = b / ax where
  * ax > 0, else 0.  b, ax, out: n device floats (projections of one block);

@@ -62,6 +62,8 @@ _SIGS = {
     "ctmi_sart_residual": (c_int, [c_p, c_p, c_p, c_p, c_i64, c_p]),
     "ctmi_sart_update": (c_int, [c_p, c_p, c_p, c_i64, c_f, c_int, c_p]),
     "ctmi_em_ratio": (c_int, [c_p, c_p, c_p, c_i64, c_p]),
+    "ctmi_awtv_grad": (c_int, [c_p, c_p, c_i64, c_i64, c_i64, c_f, c_f, c_p]),
+    "ctmi_tv_step": (c_int, [c_p, c_p, c_i64, c_p, c_f, c_p]),
     "ctmi_em_update": (c_int, [c_p, c_p, c_p, c_i64, c_p]),
     "ctmi_fov_sq_err": (c_int, [c_p, c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
     # learned prior (ctmi_unet.h)

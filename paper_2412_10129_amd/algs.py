@@ -124,17 +124,23 @@ class OSSART:
         self._e = torch.empty(plan.proj_shape(mb), dtype=torch.float32, device=dev)
         self._bp = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
 
+    def sweep(self, x: torch.Tensor, b: torch.Tensor, lam: float = 1.0, nonneg: bool = True) -> torch.Tensor:
+        """One pass over all blocks, in place on x."""
+        plan = self.plan
+        for s, (v0, nb) in enumerate(self.blocks):
+            e = self._e[:nb]
+            plan.forward(x, out=e, kind=self.kind, view0=v0, nviews=nb)
+            ops.sart_residual(b[v0:v0 + nb], e, self.W[v0:v0 + nb], e)
+            plan.backproject(e, out=self._bp, kind=self.kind, view0=v0, nviews=nb)
+            ops.sart_update(x, self.V[s], self._bp, lam, nonneg)
+        return x
+
     def run(self, b: torch.Tensor, niter: int, lam: float = 1.0, nonneg: bool = True,
             x0: Optional[torch.Tensor] = None) -> torch.Tensor:
         plan = self.plan
         x = torch.zeros(plan.vol_shape, dtype=torch.float32, device=plan.device) if x0 is None else x0.clone()
         for _ in range(niter):
-            for s, (v0, nb) in enumerate(self.blocks):
-                e = self._e[:nb]
-                plan.forward(x, out=e, kind=self.kind, view0=v0, nviews=nb)
-                ops.sart_residual(b[v0:v0 + nb], e, self.W[v0:v0 + nb], e)
-                plan.backproject(e, out=self._bp, kind=self.kind, view0=v0, nviews=nb)
-                ops.sart_update(x, self.V[s], self._bp, lam, nonneg)
+            self.sweep(x, b, lam, nonneg)
         return x
 
 
@@ -191,6 +197,73 @@ def mlem(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp",
 def osem(plan: Plan, b: torch.Tensor, niter: int, blocksize: int, kind: str = "interp",
          x0: Optional[torch.Tensor] = None) -> torch.Tensor:
     return OSEM(plan, blocksize, kind).run(b, niter, x0)
+
+
+class ASDPOCS:
+    """ASD-POCS and OS-ASD-POCS (section 2.2: the POCS class, a data step
+    alternated with adaptive TV steepest descent; OS version over blocks of
+    views, section 2.2.2; adaptive-weighted TV for finite delta, section
+    2.2.3), following Sidky and Pan.  Per iteration: one OS-SART pass with
+    step lam (x >= 0 after each block if nonneg); dd = |A x - b| and
+    dp = |change of the pass| (the first iteration sets the TV step
+    dtvg = alpha dp); ng steps x -= dtvg g / |g|, g the (Aw)TV gradient;
+    dg = |change of the TV steps|; if dg > rmax dp and dd > eps_data,
+    dtvg *= alpha_red; lam *= lam_red.  The three norms are read on the host
+    once per iteration (the step rule needs them); everything else stays on
+    the device."""
+
+    def __init__(self, plan: Plan, blocksize: int = 1, kind: str = "interp"):
+        self.plan, self.kind = plan, kind
+        self.sart = OSSART(plan, blocksize, kind)
+        dev = plan.device
+        self._prev = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+        self._g = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+        self._res = torch.empty(plan.proj_shape(), dtype=torch.float32, device=dev)
+        self._gn = torch.empty(1, dtype=torch.float64, device=dev)
+        self._nrm = torch.empty(3, dtype=torch.float64, device=dev)
+        self._ws = ops._ws(dev)
+
+    def _dist2(self, x: torch.Tensor, ref: torch.Tensor, slot: int) -> None:
+        """|x - ref|^2 into self._nrm[slot]; ref is overwritten by x - ref."""
+        ops.axpby(1.0, x, -1.0, ref)
+        ops.dot(ref, ref, out=self._nrm[slot:slot + 1], ws=self._ws)
+
+    def run(self, b: torch.Tensor, niter: int, lam: float = 1.0, lam_red: float = 0.99, alpha: float = 0.002,
+            alpha_red: float = 0.95, ng: int = 20, rmax: float = 0.95, eps_data: float = 0.0,
+            delta: float = float("inf"), eps_tv: float = 1e-8, nonneg: bool = True,
+            x0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        plan = self.plan
+        x = torch.zeros(plan.vol_shape, dtype=torch.float32, device=plan.device) if x0 is None else x0.clone()
+        dtvg = None
+        for _ in range(niter):
+            self._prev.copy_(x)
+            self.sart.sweep(x, b, lam, nonneg)
+            plan.forward(x, out=self._res, kind=self.kind)
+            self._dist2(b, self._res, 0)            # |b - A x|^2 (sign irrelevant)
+            self._dist2(x, self._prev, 1)           # |x - x_prev|^2
+            self._prev.copy_(x)
+            for _ in range(ng):
+                ops.awtv_grad(x, out=self._g, delta=delta, eps=eps_tv)
+                ops.dot(self._g, self._g, out=self._gn, ws=self._ws)
+                if dtvg is None:
+                    # the first TV step length needs dp (one host read)
+                    dtvg = alpha * float(self._nrm[1].item()) ** 0.5
+                ops.tv_step(x, self._g, self._gn, dtvg)
+            self._dist2(x, self._prev, 2)           # |x - x_before_tv|^2
+            dd, dp, dg = (float(v) ** 0.5 for v in self._nrm.cpu())
+            if dtvg is None:
+                dtvg = alpha * dp
+            if dg > rmax * dp and dd > eps_data:
+                dtvg *= alpha_red
+            lam *= lam_red
+        return x
+
+
+def asd_pocs(plan: Plan, b: torch.Tensor, niter: int, blocksize: int = 1, kind: str = "interp",
+             **kw) -> torch.Tensor:
+    """ASD-POCS (blocksize 1: SART data steps); OS-ASD-POCS for blocksize > 1;
+    AwTV-ASD-POCS with a finite delta."""
+    return ASDPOCS(plan, blocksize, kind).run(b, niter, **kw)
 
 
 def pnp_cgls(plan: Plan, b: torch.Tensor, niter: int, denoiser, every: int = 5, ratio: float = 1.05,

@@ -495,6 +495,30 @@ int ctmi_sart_update(float* x, const float* v, const float* bp, int64_t n, float
                     "sart_update");
 }
 
+int ctmi_awtv_grad(const float* x, float* g, int64_t nz, int64_t ny, int64_t nx, float delta, float eps, void* stream)
+{
+    int rc;
+    if ((rc = check_ptr(x, "x")) || (rc = check_ptr(g, "g"))) return rc;
+    if (nz < 1 || ny < 1 || nx < 1) return fail(CTMI_EINVAL, "volume dimensions must be >= 1");
+    if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20) || (double)nx * ny * nz >= 2147483648.0)
+        return fail(CTMI_EOVERFLOW, "volume must hold < 2^31 voxels");
+    if (x == g) return fail(CTMI_EINVAL, "g must not alias x");
+    if (std::isnan(delta)) return fail(CTMI_EINVAL, "delta is NaN");
+    if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(CTMI_EINVAL, "eps must be finite and >= 0");
+    return launched(ctmi::launch_awtv_grad(x, g, (int)nz, (int)ny, (int)nx, delta, eps, static_cast<hipStream_t>(stream)),
+                    "awtv_grad");
+}
+
+int ctmi_tv_step(float* x, const float* g, int64_t n, const double* gnorm2, float step, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n)) || (rc = check_ptr(x, "x")) || (rc = check_ptr(g, "g"))) return rc;
+    if (!gnorm2) return fail(CTMI_EINVAL, "gnorm2 is NULL");
+    if (!std::isfinite(step)) return fail(CTMI_EINVAL, "step is not finite");
+    if (n == 0) return CTMI_OK;
+    return launched(ctmi::launch_tv_step(x, g, n, gnorm2, step, static_cast<hipStream_t>(stream)), "tv_step");
+}
+
 int ctmi_em_ratio(const float* b, const float* ax, float* out, int64_t n, void* stream)
 {
     int rc;

@@ -106,6 +106,8 @@ hipError_t launch_sart_residual(const float* b, const float* ax, const float* w,
 hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t n, float lam, int nonneg,
                               hipStream_t s);
 hipError_t launch_em_ratio(const float* b, const float* ax, float* out, int64_t n, hipStream_t s);
+hipError_t launch_awtv_grad(const float* x, float* g, int nz, int ny, int nx, float delta, float eps, hipStream_t s);
+hipError_t launch_tv_step(float* x, const float* g, int64_t n, const double* gnorm2, float step, hipStream_t s);
 hipError_t launch_em_update(float* x, const float* v, const float* bp, int64_t n, hipStream_t s);
 hipError_t launch_fov_sq_err(const Plan& p, const float* x, const float* gt, double* out, double* ws,
                              hipStream_t s);

@@ -123,6 +123,78 @@ __global__ void __launch_bounds__(256) k_sart_update(float* __restrict__ x, cons
     }
 }
 
+// Adaptive-weighted TV (section 2.2.3, extended to 3-D): the term of voxel
+// u (all three backward neighbours present) is s_u = sqrt(sum_a w_a d_a^2 +
+// eps), d_a = x_u - x_{u - e_a}, w_a = exp(-(d_a / delta)^2) (1 for plain
+// TV); q_a(u) = w_a d_a / s_u (0 when s_u = 0).  The gradient with the
+// weights lagged is g_v = sum_a q_a(v) - sum_a q_a(v + e_a).  One thread per
+// voxel reads its 13-point neighbourhood (neighbouring threads share it
+// through the caches) and forms the four terms it needs.
+struct TvTerm {
+    float qz, qy, qx;
+};
+
+__device__ __forceinline__ TvTerm tv_term(float c, float bz, float by, float bx, float nid2, float eps)
+{
+    const float dz = c - bz, dy = c - by, dx = c - bx;
+    float wz = 1.0f, wy = 1.0f, wx = 1.0f;
+    if (nid2 != 0.0f) {   // nid2 = -1 / delta^2
+        wz = __expf(dz * dz * nid2);
+        wy = __expf(dy * dy * nid2);
+        wx = __expf(dx * dx * nid2);
+    }
+    const float az = wz * dz, ay = wy * dy, ax = wx * dx;
+    const float s2 = __builtin_fmaf(az, dz, __builtin_fmaf(ay, dy, __builtin_fmaf(ax, dx, eps)));
+    const float r = s2 > 0.0f ? 1.0f / __builtin_sqrtf(s2) : 0.0f;
+    return TvTerm{az * r, ay * r, ax * r};
+}
+
+__global__ void __launch_bounds__(256) k_awtv_grad(const float* __restrict__ x, float* __restrict__ g, int nz, int ny,
+                                                   int nx, float nid2, float eps)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ix = (int)(i % nx);
+    const int64_t r = i / nx;
+    const int iy = (int)(r % ny), iz = (int)(r / ny);
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const float c = x[i];
+    float gv = 0.0f;
+    // own term
+    if (ix > 0 && iy > 0 && iz > 0) {
+        const TvTerm t = tv_term(c, x[i - sz], x[i - sy], x[i - 1], nid2, eps);
+        gv = t.qz + t.qy + t.qx;
+    }
+    // terms of the forward neighbours, in which x_v is the backward value
+    if (iz + 1 < nz && ix > 0 && iy > 0) {
+        const int64_t u = i + sz;
+        gv -= tv_term(x[u], c, x[u - sy], x[u - 1], nid2, eps).qz;
+    }
+    if (iy + 1 < ny && ix > 0 && iz > 0) {
+        const int64_t u = i + sy;
+        gv -= tv_term(x[u], x[u - sz], c, x[u - 1], nid2, eps).qy;
+    }
+    if (ix + 1 < nx && iy > 0 && iz > 0) {
+        const int64_t u = i + 1;
+        gv -= tv_term(x[u], x[u - sz], x[u - sy], c, nid2, eps).qx;
+    }
+    g[i] = gv;
+}
+
+// TV steepest-descent step: x -= step * g / sqrt(gnorm2) (gnorm2 a device
+// double; nothing happens when it is 0).
+__global__ void __launch_bounds__(256) k_tv_step(float* __restrict__ x, const float* __restrict__ g, int64_t n,
+                                                 const double* __restrict__ gnorm2, float step)
+{
+    const double gn2 = *gnorm2;
+    if (!(gn2 > 0.0)) return;
+    const float f = (float)((double)step / sqrt(gn2));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        x[i] = __builtin_fmaf(-f, g[i], x[i]);
+}
+
 // EM ratio (MLEM/OSEM, section 2.2): out = b / ax where ax > 0, else 0.
 __global__ void __launch_bounds__(256) k_em_ratio(const float* __restrict__ b, const float* ax, float* out, int64_t n)
 {
@@ -231,6 +303,21 @@ hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t
                               hipStream_t s)
 {
     hipLaunchKernelGGL(k_sart_update, dim3(stream_blocks(n)), dim3(256), 0, s, x, v, bp, n, lam, nonneg);
+    return hipGetLastError();
+}
+
+hipError_t launch_awtv_grad(const float* x, float* g, int nz, int ny, int nx, float delta, float eps, hipStream_t s)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    // -1 / delta^2, or 0 for plain TV (delta <= 0 or infinite)
+    const float nid2 = (delta > 0.0f && delta < CTMI_INF) ? -1.0f / (delta * delta) : 0.0f;
+    hipLaunchKernelGGL(k_awtv_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, g, nz, ny, nx, nid2, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_step(float* x, const float* g, int64_t n, const double* gnorm2, float step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tv_step, dim3(stream_blocks(n)), dim3(256), 0, s, x, g, n, gnorm2, step);
     return hipGetLastError();
 }
 

@@ -199,3 +199,23 @@ def em_update(x, v, bp, stream=None):
     n = x.numel()
     L.check(L.lib().ctmi_em_update(_ptr(x, "x"), _ptr(v, "v", n), _ptr(bp, "bp", n), n, _stream(stream)))
     return x
+
+
+def awtv_grad(x: torch.Tensor, out: Optional[torch.Tensor] = None, delta: float = float("inf"), eps: float = 1e-8,
+              stream=None) -> torch.Tensor:
+    """Gradient of the (adaptive-weighted) total variation of a [nz, ny, nx]
+    volume, weights lagged; plain TV for delta = inf."""
+    if x.dim() != 3:
+        raise ValueError("x must be a [nz, ny, nx] volume")
+    out = torch.empty_like(x) if out is None else out
+    nz, ny, nx = x.shape
+    L.check(L.lib().ctmi_awtv_grad(_ptr(x, "x"), _ptr(out, "g", x.numel()), nz, ny, nx, float(delta), float(eps),
+                                   _stream(stream)))
+    return out
+
+
+def tv_step(x: torch.Tensor, g: torch.Tensor, gnorm2: torch.Tensor, step: float, stream=None) -> torch.Tensor:
+    """x -= step * g / sqrt(gnorm2) (gnorm2: 1-element float64 device tensor)."""
+    L.check(L.lib().ctmi_tv_step(_ptr(x, "x"), _ptr(g, "g", x.numel()), x.numel(),
+                                 ctypes.c_void_p(gnorm2.data_ptr()), float(step), _stream(stream)))
+    return x

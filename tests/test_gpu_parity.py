@@ -263,6 +263,66 @@ def test_em_elementwise_kernels_bit_exact(P):
     assert np.array_equal(_host(xd), (x * v) * bp)
 
 
+@pytest.mark.parametrize("delta", [float("inf"), 0.25])
+@pytest.mark.parametrize("shape", [(17, 19, 23), (1, 8, 9), (6, 1, 5), (1, 1, 1)])
+def test_awtv_grad_matches_oracle(P, orc, delta, shape):
+    """(Aw)TV gradient on a random volume with a voxel-aligned block added
+    (edges where the adaptive weights switch off), ragged and degenerate
+    shapes (a single plane or voxel has no interior terms: g = 0).  FP32
+    terms take about ten roundings each and a voxel sums four of them:
+    bar 1e-5 relative."""
+    from paper_2412_10129_amd import ops
+    rng = np.random.Generator(np.random.PCG64(22))
+    x = rng.random(shape) * 0.3
+    x[shape[0] // 3: 2 * shape[0] // 3 + 1, shape[1] // 4: 3 * shape[1] // 4 + 1, 2:] += 1.0
+    x = x.astype(np.float32)
+    got = _host(ops.awtv_grad(_dev(x), delta=delta, eps=1e-8))
+    want = orc.awtv_grad(x.astype(np.float64), delta, 1e-8)
+    if not np.any(want):
+        assert not np.any(got)
+    else:
+        assert _rel(got, want) < 1e-5, _rel(got, want)
+
+
+def test_tv_step_matches_numpy(P):
+    from paper_2412_10129_amd import ops
+    rng = np.random.Generator(np.random.PCG64(23))
+    x = rng.random(50001).astype(np.float32)
+    g = rng.standard_normal(50001).astype(np.float32)
+    gd = _dev(g)
+    gn = ops.dot(gd, gd)
+    xd = _dev(x)
+    ops.tv_step(xd, gd, gn, 0.37)
+    want = x.astype(np.float64) - 0.37 * g / np.linalg.norm(g.astype(np.float64))
+    assert _rel(_host(xd), want) < 1e-6
+    zero = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ops.tv_step(xd, gd, zero, 0.37)            # |g| = 0: no change
+    assert _rel(_host(xd), want) < 1e-6
+
+
+@pytest.mark.parametrize("blocksize,rmax,delta", [(1, 1e9, float("inf")), (4, 0.0, float("inf")),
+                                                  (4, 1e9, 0.5)])
+def test_asd_pocs_matches_oracle(P, orc, blocksize, rmax, delta):
+    """ASD-POCS (SART data steps), OS-ASD-POCS and AwTV-OS-ASD-POCS, 2
+    iterations of 10 TV steps against the oracle.  rmax = 1e9 never shrinks
+    the TV step and rmax = 0 always does, so both sides take the same
+    branch.  Fixed-length TV steps amplify small differences: the oracle
+    itself moves by at most 8e-5 (relative) when the data are perturbed by
+    1e-5, the FP32 operators' own error level, so the bar is 1e-3."""
+    geo = Geometry(DSD=400.0, DSO=250.0, nVoxel=(20, 24, 28), dVoxel=(1.0, 1.0, 1.0), nDetector=(30, 40),
+                   dDetector=(1.3, 1.3))
+    ang = synth.circular_angles(16)
+    xt = np.zeros(geo.nVoxel)
+    xt[4:16, 5:19, 6:22] = 1.0
+    xt[8:12, 9:15, 10:18] = 1.5
+    b = orc.forward(geo, ang, xt, "interp").astype(np.float32)
+    plan = P.Plan(geo, ang)
+    kw = dict(alpha=0.002, ng=10, rmax=rmax, delta=delta)
+    got = _host(P.asd_pocs(plan, _dev(b), 2, blocksize=blocksize, kind="interp", **kw))
+    want = orc.asd_pocs(geo, ang, b.astype(np.float64), 2, blocksize=blocksize, kind="interp", **kw)
+    assert _rel(got, want) < 1e-3, _rel(got, want)
+
+
 @pytest.mark.parametrize("kind", ["siddon", "interp"])
 def test_backproject_heavy_tailed_projections(P, orc, kind):
     """A^T of projections whose values span four decades (one pixel in a
