@@ -338,6 +338,55 @@ def main():
             breakdown[name] = ent
             print(f"[bench] {name}: {ent}", flush=True)
 
+        # the wider solver rows at the same size: elementwise and stencil
+        # kernels against their algorithmic HBM bytes, one MLEM iteration and
+        # one OS-ASD-POCS iteration (blocks of 20 views, 20 AwTV steps)
+        from paper_2412_10129_amd import ops as O
+        from paper_2412_10129_amd import algs as AL
+        nvox = x.numel()
+        xs = x.clone()
+        bps = s.clone()
+        gn = O.dot(s, s)
+        extra = [
+            ("awtv_grad", lambda: O.awtv_grad(x, out=s, delta=0.5), 8.0 * nvox),
+            ("tv_step", lambda: O.tv_step(xs, s, gn, 1e-3), 12.0 * nvox),
+            ("em_ratio", lambda: O.em_ratio(b, q, q), 12.0 * b.numel()),
+            ("em_update", lambda: O.em_update(xs, bps, bps), 16.0 * nvox),
+        ]
+        for name, fn, nbytes in extra:
+            fn()
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(stream)
+            for _ in range(3):
+                fn()
+            eb.record(stream)
+            torch.cuda.synchronize()
+            t = ea.elapsed_time(eb) / 3
+            ent = {"ms": round(t, 3), "GB/s": round(nbytes / (t / 1e3) / 1e9, 1),
+                   "frac_hbm": round(nbytes / (t / 1e3) / 8e12, 3)}
+            breakdown[name] = ent
+            print(f"[bench] {name}: {ent}", flush=True)
+        del xs, bps
+        for name, make, it in (("mlem_iter", lambda: AL.OSEM(plan, None, kind), None),
+                               ("os_asd_pocs_iter", lambda: AL.ASDPOCS(plan, 20, kind), None)):
+            solver = make()
+            torch.cuda.synchronize()
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(stream)
+            if name == "mlem_iter":
+                xm = torch.ones_like(x)
+                solver.step(xm, b)
+            else:
+                solver.run(b, 1)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            t = ea.elapsed_time(eb)
+            breakdown[name] = {"ms": round(t, 1), "updates/s": float(f"{2 * upd / (t / 1e3):.4g}")}
+            print(f"[bench] {name}: {breakdown[name]}", flush=True)
+            del solver
+
     learned = None
     if not args.no_learned:
         # the second half of the headline metric: time to 40 dB of the learned
