@@ -149,37 +149,110 @@ __device__ __forceinline__ TvTerm tv_term(float c, float bz, float by, float bx,
     return TvTerm{az * r, ay * r, ax * r};
 }
 
+// Tiled form: a workgroup owns a 64 x 8 (x, y) column of the volume over
+// TZ consecutive planes and marches up z.  Each step stages plane z + 1 (with
+// a one-voxel lower halo in x and y) in LDS, forms the terms of plane z + 1
+// once for the tile and its upper halo, and finishes plane z's gradient from
+// the terms of planes z and z + 1.  The plane after is loaded into registers
+// while the step runs.
+constexpr int TVX = 64, TVY = 8, TVZ = 64;
+constexpr int TXH = TVX + 2, TYH = TVY + 2;          // staged plane with lower and upper halo
+constexpr int TQX = TVX + 1, TQY = TVY + 1;          // terms: tile plus upper halo
+constexpr int TVL = (TXH * TYH + 255) / 256;         // staged cells per thread
+
 __global__ void __launch_bounds__(256) k_awtv_grad(const float* __restrict__ x, float* __restrict__ g, int nz, int ny,
                                                    int nx, float nid2, float eps)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int ix = (int)(i % nx);
-    const int64_t r = i / nx;
-    const int iy = (int)(r % ny), iz = (int)(r / ny);
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const float c = x[i];
-    float gv = 0.0f;
-    // own term
-    if (ix > 0 && iy > 0 && iz > 0) {
-        const TvTerm t = tv_term(c, x[i - sz], x[i - sy], x[i - 1], nid2, eps);
-        gv = t.qz + t.qy + t.qx;
+    __shared__ float pl[2][TXH * TYH];   // planes z and z + 1 (x from x0 - 1, y from y0 - 1)
+    __shared__ float q[2][3][TQX * TQY]; // terms (z, y, x components) of planes z and z + 1
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TVX, y0 = blockIdx.y * TVY, z0 = blockIdx.z * TVZ;
+    const int z1 = min(z0 + TVZ, nz);
+    const int64_t sz = (int64_t)nx * ny;
+    // staged cells of this thread: c -> (x0 - 1 + c % TXH, y0 - 1 + c / TXH)
+    int64_t off[TVL];
+    bool in[TVL];
+#pragma unroll
+    for (int m = 0; m < TVL; ++m) {
+        const int c = tid + 256 * m;
+        const int X = x0 - 1 + c % TXH, Y = y0 - 1 + c / TXH;
+        in[m] = c < TXH * TYH && X >= 0 && X < nx && Y >= 0 && Y < ny;
+        off[m] = in[m] ? (int64_t)Y * nx + X : 0;
     }
-    // terms of the forward neighbours, in which x_v is the backward value
-    if (iz + 1 < nz && ix > 0 && iy > 0) {
-        const int64_t u = i + sz;
-        gv -= tv_term(x[u], c, x[u - sy], x[u - 1], nid2, eps).qz;
+    auto fetch = [&](int Z, float (&r)[TVL]) {
+#pragma unroll
+        for (int m = 0; m < TVL; ++m) r[m] = (in[m] && Z >= 0 && Z < nz) ? x[(int64_t)Z * sz + off[m]] : 0.0f;
+    };
+    auto stage = [&](float* dst, const float (&r)[TVL]) {
+#pragma unroll
+        for (int m = 0; m < TVL; ++m) {
+            const int c = tid + 256 * m;
+            if (c < TXH * TYH) dst[c] = r[m];
+        }
+    };
+    // terms of plane Z from its staged plane cur and the plane below, prev
+    auto terms = [&](int Z, const float* cur, const float* prev, int slot) {
+        for (int c = tid; c < TQX * TQY; c += 256) {
+            const int i = c % TQX, j = c / TQX;
+            const int X = x0 + i, Y = y0 + j;
+            float qz = 0.0f, qy = 0.0f, qx = 0.0f;
+            if (X >= 1 && Y >= 1 && Z >= 1 && X < nx && Y < ny && Z < nz) {
+                const int k = (j + 1) * TXH + (i + 1);
+                const TvTerm t = tv_term(cur[k], prev[k], cur[k - TXH], cur[k - 1], nid2, eps);
+                qz = t.qz;
+                qy = t.qy;
+                qx = t.qx;
+            }
+            q[slot][0][c] = qz;
+            q[slot][1][c] = qy;
+            q[slot][2][c] = qx;
+        }
+    };
+    int cp = 0, cq = 0;   // LDS slots holding plane z and its terms
+    {
+        float r[TVL];
+        fetch(z0 - 1, r);
+        stage(pl[1], r);
+        fetch(z0, r);
+        stage(pl[0], r);
     }
-    if (iy + 1 < ny && ix > 0 && iz > 0) {
-        const int64_t u = i + sy;
-        gv -= tv_term(x[u], x[u - sz], c, x[u - 1], nid2, eps).qy;
+    __syncthreads();
+    terms(z0, pl[0], pl[1], 0);
+    // planes z + 1 ... z + 4 in flight in registers (global-load latency is
+    // longer than one step)
+    float ra[TVL], rb[TVL], rc[TVL], rd[TVL];
+    fetch(z0 + 1, ra);
+    fetch(z0 + 2, rb);
+    fetch(z0 + 3, rc);
+    fetch(z0 + 4, rd);
+    auto step = [&](int z, float (&r)[TVL]) {
+        // stage plane z + 1 over the slot of plane z - 1, then refill the
+        // registers with plane z + 5
+        stage(pl[cp ^ 1], r);
+        __syncthreads();
+        fetch(z + 5, r);
+        terms(z + 1, pl[cp ^ 1], pl[cp], cq ^ 1);
+        __syncthreads();
+#pragma unroll
+        for (int o = tid; o < TVX * TVY; o += 256) {
+            const int tx = o % TVX, ty = o / TVX;
+            const int X = x0 + tx, Y = y0 + ty;
+            if (X < nx && Y < ny) {
+                const int k = ty * TQX + tx;
+                const float gv = q[cq][0][k] + q[cq][1][k] + q[cq][2][k] - q[cq ^ 1][0][k] - q[cq][1][k + TQX] -
+                                 q[cq][2][k + 1];
+                g[(int64_t)z * sz + (int64_t)Y * nx + X] = gv;
+            }
+        }
+        cp ^= 1;
+        cq ^= 1;
+    };
+    for (int z = z0; z < z1; z += 4) {
+        step(z, ra);
+        if (z + 1 < z1) step(z + 1, rb);
+        if (z + 2 < z1) step(z + 2, rc);
+        if (z + 3 < z1) step(z + 3, rd);
     }
-    if (ix + 1 < nx && iy > 0 && iz > 0) {
-        const int64_t u = i + 1;
-        gv -= tv_term(x[u], x[u - sz], x[u - sy], c, nid2, eps).qx;
-    }
-    g[i] = gv;
 }
 
 // TV steepest-descent step: x -= step * g / sqrt(gnorm2) (gnorm2 a device
@@ -308,10 +381,10 @@ hipError_t launch_sart_update(float* x, const float* v, const float* bp, int64_t
 
 hipError_t launch_awtv_grad(const float* x, float* g, int nz, int ny, int nx, float delta, float eps, hipStream_t s)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
     // -1 / delta^2, or 0 for plain TV (delta <= 0 or infinite)
     const float nid2 = (delta > 0.0f && delta < CTMI_INF) ? -1.0f / (delta * delta) : 0.0f;
-    hipLaunchKernelGGL(k_awtv_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, g, nz, ny, nx, nid2, eps);
+    const dim3 grid((unsigned)((nx + TVX - 1) / TVX), (unsigned)((ny + TVY - 1) / TVY), (unsigned)((nz + TVZ - 1) / TVZ));
+    hipLaunchKernelGGL(k_awtv_grad, grid, dim3(256), 0, s, x, g, nz, ny, nx, nid2, eps);
     return hipGetLastError();
 }
 
