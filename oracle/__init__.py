@@ -12,6 +12,7 @@ order.  Every function names the passage of the paper it follows.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import math
 import os
 import subprocess
@@ -19,7 +20,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from synth import Ellipsoid, Geometry
+from synth import Ellipsoid, Geometry, Views
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ctoracle.c")
@@ -68,6 +69,51 @@ def _geo(g: Geometry) -> _Geo:
                 *g.offDetector, g.accuracy)
 
 
+class _View(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("z1", "y1", "z2", "DSO", "DSD", "oz", "oy", "ox", "ov", "ou", "cor",
+                                               "roll", "pitch", "yaw")]
+
+
+class _Mode:
+    """Circular views (angles: 1-D z1 array) or per-view frames (synth.Views):
+    the C oracle takes the frames through orc_set_views for the duration of
+    one call; the volume box is then centred at the origin and each view's
+    rays are expressed relative to its own volume centre."""
+
+    def __init__(self, geo: Geometry, angles):
+        self.views = angles if isinstance(angles, Views) else None
+        if self.views is None:
+            self.angles = _f64(angles)
+            self.g = _geo(geo)
+        else:
+            v = self.views
+            n = len(v)
+            self.angles = np.zeros(n)
+            self.g = _geo(dataclasses.replace(geo, offOrigin=(0.0, 0.0, 0.0)))
+            self.tab = (_View * n)()
+            for k in range(n):
+                self.tab[k] = _View(*v.angles[k], v.DSO[k], v.DSD[k], *v.offOrigin[k], *v.offDetector[k], v.COR[k],
+                                    *v.rotDetector[k])
+
+    def __len__(self):
+        return len(self.angles)
+
+    def __enter__(self):
+        if self.views is not None:
+            _L().orc_set_views(self.tab, ctypes.c_int64(len(self.angles)))
+        return self
+
+    def __exit__(self, *exc):
+        if self.views is not None:
+            _L().orc_set_views(None, ctypes.c_int64(0))
+        return False
+
+
+def _angles(angles):
+    """Keep per-view Views as they are; z1 angles as float64."""
+    return angles if isinstance(angles, Views) else _f64(angles)
+
+
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -87,33 +133,30 @@ def num_threads() -> int:
 # ------------------------------------------------------------- operators
 def forward(geo: Geometry, angles, vol, kind: str = "siddon") -> np.ndarray:
     """b = A x (the paper's linear model, section 2.1, Eq. 1)."""
-    angles = _f64(angles)
     vol = _f64(vol).reshape(geo.nVoxel)
-    out = np.zeros((len(angles),) + tuple(geo.nDetector), dtype=np.float64)
-    g = _geo(geo)
-    _L().orc_forward(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(vol), _p(out))
+    with _Mode(geo, angles) as m:
+        out = np.zeros((len(m),) + tuple(geo.nDetector), dtype=np.float64)
+        _L().orc_forward(ctypes.byref(m.g), _KINDS[kind], _p(m.angles), ctypes.c_int64(len(m)), _p(vol), _p(out))
     return out
 
 
 def backward(geo: Geometry, angles, proj, kind: str = "siddon") -> np.ndarray:
     """x = A^T y, the exact transpose of `forward` (ray-driven scatter)."""
-    angles = _f64(angles)
-    proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
-    out = np.zeros(geo.nVoxel, dtype=np.float64)
-    g = _geo(geo)
-    _L().orc_backward(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(proj), _p(out))
+    with _Mode(geo, angles) as m:
+        proj = _f64(proj).reshape((len(m),) + tuple(geo.nDetector))
+        out = np.zeros(geo.nVoxel, dtype=np.float64)
+        _L().orc_backward(ctypes.byref(m.g), _KINDS[kind], _p(m.angles), ctypes.c_int64(len(m)), _p(proj), _p(out))
     return out
 
 
 def forward_rays(geo: Geometry, angles, vol, views, ivs, ius, kind: str = "siddon") -> np.ndarray:
     """(A x)_i for the listed rays only (sampled parity at full size)."""
-    angles = _f64(angles)
     vol = _f64(vol).reshape(geo.nVoxel)
     views, ivs, ius = _i64(views), _i64(ivs), _i64(ius)
     out = np.zeros(len(views), dtype=np.float64)
-    g = _geo(geo)
-    _L().orc_forward_rays(ctypes.byref(g), _KINDS[kind], _p(angles), _p(vol), ctypes.c_int64(len(views)),
-                          _p(views), _p(ivs), _p(ius), _p(out))
+    with _Mode(geo, angles) as m:
+        _L().orc_forward_rays(ctypes.byref(m.g), _KINDS[kind], _p(m.angles), _p(vol), ctypes.c_int64(len(views)),
+                              _p(views), _p(ivs), _p(ius), _p(out))
     return out
 
 
@@ -121,14 +164,13 @@ def adjoint_voxels(geo: Geometry, angles, proj, iz, iy, ix, kind: str = "siddon"
     """(A^T y)_j for the listed voxels, each matrix entry evaluated from its
     definition (cell chord, or tent sum) by brute force over the voxel's
     detector footprint."""
-    angles = _f64(angles)
-    proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
     iz, iy, ix = _i64(iz), _i64(iy), _i64(ix)
     out = np.zeros(len(iz), dtype=np.float64)
-    g = _geo(geo)
     fn = _L().orc_siddon_adjoint_voxels if kind == "siddon" else _L().orc_interp_adjoint_voxels
-    fn(ctypes.byref(g), _p(angles), ctypes.c_int64(len(angles)), _p(proj), ctypes.c_int64(len(iz)),
-       _p(iz), _p(iy), _p(ix), _p(out))
+    with _Mode(geo, angles) as m:
+        proj = _f64(proj).reshape((len(m),) + tuple(geo.nDetector))
+        fn(ctypes.byref(m.g), _p(m.angles), ctypes.c_int64(len(m)), _p(proj), ctypes.c_int64(len(iz)),
+           _p(iz), _p(iy), _p(ix), _p(out))
     return out
 
 
@@ -136,24 +178,21 @@ def gradient_voxels(geo: Geometry, angles, x, y, iz, iy, ix, kind: str = "siddon
     """2 (A^T (A x - y))_j for the listed voxels, each term from its
     definition: the voxel's footprint rays, their full ray sums and the
     matrix entries a_ij."""
-    angles = _f64(angles)
     x = _f64(x).reshape(geo.nVoxel)
-    y = _f64(y).reshape((len(angles),) + tuple(geo.nDetector))
     iz, iy, ix = _i64(iz), _i64(iy), _i64(ix)
     out = np.zeros(len(iz), dtype=np.float64)
-    g = _geo(geo)
-    _L().orc_gradient_voxels(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(x), _p(y),
-                             ctypes.c_int64(len(iz)), _p(iz), _p(iy), _p(ix), _p(out))
+    with _Mode(geo, angles) as m:
+        y = _f64(y).reshape((len(m),) + tuple(geo.nDetector))
+        _L().orc_gradient_voxels(ctypes.byref(m.g), _KINDS[kind], _p(m.angles), ctypes.c_int64(len(m)), _p(x),
+                                 _p(y), ctypes.c_int64(len(iz)), _p(iz), _p(iy), _p(ix), _p(out))
     return out
 
 
 def dense_matrix(geo: Geometry, angles, kind: str = "siddon") -> np.ndarray:
     """Explicit system matrix, every entry from its definition (tiny sizes)."""
-    angles = _f64(angles)
-    nray = geo.n_proj(len(angles))
-    M = np.zeros((nray, geo.n_vox), dtype=np.float64)
-    g = _geo(geo)
-    _L().orc_dense_matrix(ctypes.byref(g), _KINDS[kind], _p(angles), ctypes.c_int64(len(angles)), _p(M))
+    with _Mode(geo, angles) as m:
+        M = np.zeros((geo.n_proj(len(m)), geo.n_vox), dtype=np.float64)
+        _L().orc_dense_matrix(ctypes.byref(m.g), _KINDS[kind], _p(m.angles), ctypes.c_int64(len(m)), _p(M))
     return M
 
 
@@ -172,6 +211,8 @@ def bfdk(geo: Geometry, angles, proj) -> np.ndarray:
     """FDK backprojector: sum over views of (DSO/U)^2 times the bilinear
     detector sample where the source-voxel ray meets the detector (FDK, the
     paper's list of direct methods in section 2.1)."""
+    if isinstance(angles, Views):
+        raise ValueError("the FDK backprojector is defined for the circular orbit")
     angles = _f64(angles)
     proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
     out = np.zeros(geo.nVoxel, dtype=np.float64)
@@ -182,6 +223,8 @@ def bfdk(geo: Geometry, angles, proj) -> np.ndarray:
 
 def bfdk_voxels(geo: Geometry, angles, proj, iz, iy, ix) -> np.ndarray:
     """The FDK backprojector at the listed voxels only."""
+    if isinstance(angles, Views):
+        raise ValueError("the FDK backprojector is defined for the circular orbit")
     angles = _f64(angles)
     proj = _f64(proj).reshape((len(angles),) + tuple(geo.nDetector))
     iz, iy, ix = _i64(iz), _i64(iy), _i64(ix)
@@ -332,7 +375,7 @@ def os_sart(geo: Geometry, angles, b, niter: int, blocksize: int, lam: float = 1
     One iteration is one pass over all blocks.  SART is blocksize 1, SIRT
     one block.
     """
-    angles = _f64(angles)
+    angles = _angles(angles)
     b = _f64(b)
     x = np.zeros(geo.nVoxel) if x0 is None else _f64(x0).copy()
     blocks = subsets(len(angles), blocksize)
@@ -364,7 +407,7 @@ def osem(geo: Geometry, angles, b, niter: int, blocksize: Optional[int] = None, 
     (A_s^T 1)_j = 0.  Start x0 = 1 (EM needs a positive start).  One
     iteration is one pass over all blocks.
     """
-    angles = _f64(angles)
+    angles = _angles(angles)
     b = _f64(b)
     nv = len(angles)
     x = np.ones(geo.nVoxel) if x0 is None else _f64(x0).copy()
@@ -386,7 +429,7 @@ def poisson_loglik(geo: Geometry, angles, b, x, kind: str = "interp") -> float:
     """Poisson log-likelihood (up to a constant) of data b for image x:
     sum_i b_i log (A x)_i - (A x)_i over rays with (A x)_i > 0 (the quantity
     EM increases)."""
-    ax = forward(geo, _f64(angles), _f64(x), kind)
+    ax = forward(geo, _angles(angles), _f64(x), kind)
     b = _f64(b)
     pos = ax > 0
     return float(np.sum(b[pos] * np.log(ax[pos])) - np.sum(ax))
@@ -465,7 +508,7 @@ def asd_pocs(geo: Geometry, angles, b, niter: int, blocksize: int = 1, kind: str
       5. lam <- lam lam_red.
     The paper names the algorithm and its parameters without the steps;
     these follow Sidky and Pan's published description."""
-    angles = _f64(angles)
+    angles = _angles(angles)
     b = _f64(b)
     x = np.zeros(geo.nVoxel) if x0 is None else _f64(x0).copy()
     blocks = subsets(len(angles), blocksize)

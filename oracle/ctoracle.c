@@ -57,9 +57,99 @@ typedef struct {
 
 /* ------------------------------------------------------------ geometry -- */
 
-/* Source position and the centre of pixel (iv, iu) for view angle theta. */
-static void ray_endpoints(const orc_geo* g, double theta, double iv, double iu, double S[3], double P[3])
+/* Per-view geometry (the paper's section on geometric flexibility: Euler ZYZ
+ * gantry angles, centre-of-rotation shift, in-place detector rotation, and
+ * every parameter settable per projection).  Readings:
+ *   machine frame before the gantry rotation: source (DSO, COR, 0), detector
+ *   centre (DSO - DSD, COR, 0), detector axes u = (0, 1, 0), v = (0, 0, 1),
+ *   normal (1, 0, 0) towards the source;
+ *   detector rotation about its centre (roll about the normal x, pitch about
+ *   u = y, yaw about v = z): R_d = Rx(roll) Ry(pitch) Rz(yaw);
+ *   detector offsets are taken along the rotated detector axes;
+ *   gantry rotation about the origin: R_g = Rz(z1) Ry(y1) Rz(z2);
+ *   offOrigin moves the volume: rays are expressed relative to it.
+ * With (z1, 0, 0) and everything else zero this is the circular default. */
+typedef struct {
+    double z1, y1, z2;
+    double DSO, DSD;
+    double oz, oy, ox;   /* volume centre (mm) */
+    double ov, ou;       /* detector offset (mm) */
+    double cor;          /* mm */
+    double roll, pitch, yaw;
+} orc_view;
+
+/* when set, ray_endpoints and the footprints use these frames instead of the
+ * circular default (the Python wrapper sets it around one call) */
+static const orc_view* g_views = NULL;
+static int64_t g_nviews = 0;
+
+void orc_set_views(const orc_view* v, int64_t n)
 {
+    g_views = n > 0 ? v : NULL;
+    g_nviews = n;
+}
+
+static void rot_x(double a, const double in[3], double out[3])
+{
+    const double c = cos(a), s = sin(a);
+    out[0] = in[0];
+    out[1] = c * in[1] - s * in[2];
+    out[2] = s * in[1] + c * in[2];
+}
+
+static void rot_y(double a, const double in[3], double out[3])
+{
+    const double c = cos(a), s = sin(a);
+    out[0] = c * in[0] + s * in[2];
+    out[1] = in[1];
+    out[2] = -s * in[0] + c * in[2];
+}
+
+static void rot_z(double a, const double in[3], double out[3])
+{
+    const double c = cos(a), s = sin(a);
+    out[0] = c * in[0] - s * in[1];
+    out[1] = s * in[0] + c * in[1];
+    out[2] = in[2];
+}
+
+/* world (volume-relative) source, detector centre and unit detector axes of
+ * view k */
+static void view_frame(const orc_view* w, double S[3], double D[3], double eu[3], double ev[3])
+{
+    double t[3], t2[3];
+    const double s0[3] = {w->DSO, w->cor, 0.0}, d0[3] = {w->DSO - w->DSD, w->cor, 0.0};
+    const double u0[3] = {0.0, 1.0, 0.0}, v0[3] = {0.0, 0.0, 1.0};
+    double ud[3], vd[3];
+    /* detector rotation: yaw, then pitch, then roll */
+    rot_z(w->yaw, u0, t); rot_y(w->pitch, t, t2); rot_x(w->roll, t2, ud);
+    rot_z(w->yaw, v0, t); rot_y(w->pitch, t, t2); rot_x(w->roll, t2, vd);
+    const double* in[4] = {s0, d0, ud, vd};
+    double* out[4] = {S, D, eu, ev};
+    for (int i = 0; i < 4; ++i) {
+        rot_z(w->z2, in[i], t); rot_y(w->y1, t, t2); rot_z(w->z1, t2, out[i]);
+    }
+    const double o[3] = {w->ox, w->oy, w->oz};
+    for (int a = 0; a < 3; ++a) {
+        S[a] -= o[a];
+        D[a] -= o[a];
+    }
+}
+
+/* Source position and the centre of pixel (iv, iu) of view k. */
+static void ray_endpoints(const orc_geo* g, const double* angles, int64_t k, double iv, double iu, double S[3],
+                          double P[3])
+{
+    if (g_views) {
+        const orc_view* w = &g_views[k];
+        double D[3], eu[3], ev[3];
+        view_frame(w, S, D, eu, ev);
+        const double u = (iu + 0.5 - 0.5 * (double)g->nu) * g->du + w->ou;
+        const double v = (iv + 0.5 - 0.5 * (double)g->nv) * g->dv + w->ov;
+        for (int a = 0; a < 3; ++a) P[a] = D[a] + u * eu[a] + v * ev[a];
+        return;
+    }
+    const double theta = angles[k];
     const double c = cos(theta), s = sin(theta);
     const double u = (iu + 0.5 - 0.5 * (double)g->nu) * g->du + g->ou;
     const double v = (iv + 0.5 - 0.5 * (double)g->nv) * g->dv + g->ov;
@@ -74,7 +164,7 @@ static void ray_endpoints(const orc_geo* g, double theta, double iv, double iu, 
 
 void orc_ray_endpoints(const orc_geo* g, double theta, double iv, double iu, double* S, double* P)
 {
-    ray_endpoints(g, theta, iv, iu, S, P);
+    ray_endpoints(g, &theta, 0, iv, iu, S, P);
 }
 
 /* volume box: lo[a], cell size h[a], count n[a] for a = x, y, z */
@@ -296,7 +386,7 @@ void orc_forward(const orc_geo* g, int kind, const double* angles, int64_t nview
             const int64_t k = row / g->nv, iv = row % g->nv;
             for (int64_t iu = 0; iu < g->nu; ++iu) {
                 double S[3], P[3];
-                ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+                ray_endpoints(g, angles, k, (double)iv, (double)iu, S, P);
                 proj[row * g->nu + iu] = ray_sum(g, kind, S, P, vol, cell, len, wa);
             }
         }
@@ -317,7 +407,7 @@ void orc_forward_rays(const orc_geo* g, int kind, const double* angles, const do
         #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < nrays; ++i) {
             double S[3], P[3];
-            ray_endpoints(g, angles[view[i]], (double)iv[i], (double)iu[i], S, P);
+            ray_endpoints(g, angles, view[i], (double)iv[i], (double)iu[i], S, P);
             out[i] = ray_sum(g, kind, S, P, vol, cell, len, wa);
         }
         free(cell); free(len); free(wa);
@@ -354,7 +444,7 @@ void orc_backward(const orc_geo* g, int kind, const double* angles, int64_t nvie
                 const double y = proj[row * g->nu + iu];
                 if (y == 0.0) continue;
                 double S[3], P[3];
-                ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+                ray_endpoints(g, angles, k, (double)iv, (double)iu, S, P);
                 ray_scatter(g, kind, S, P, y, acc, cell, len, wa);
             }
         }
@@ -391,21 +481,42 @@ static double box_chord(const double S[3], const double P[3], const double bl[3]
 
 /* Detector pixel index range [iu0, iu1] x [iv0, iv1] that can see the box
  * [bl, bh] in view theta: project its 8 corners, pad by one pixel. */
-static int box_footprint(const orc_geo* g, double theta, const double bl[3], const double bh[3], int64_t* iu0,
-                         int64_t* iu1, int64_t* iv0, int64_t* iv1)
+static int box_footprint(const orc_geo* g, const double* angles, int64_t k, const double bl[3], const double bh[3],
+                         int64_t* iu0, int64_t* iu1, int64_t* iv0, int64_t* iv1)
 {
-    const double c = cos(theta), s = sin(theta);
     double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+    /* pixel index coordinates of the central projection of each box corner:
+     * from the pixel grid of view k (pixel (0,0) centre, axis steps) */
+    double S[3], P00[3], P10[3], P01[3];
+    ray_endpoints(g, angles, k, 0.0, 0.0, S, P00);
+    ray_endpoints(g, angles, k, 0.0, 1.0, S, P10);
+    ray_endpoints(g, angles, k, 1.0, 0.0, S, P01);
+    double eu[3], ev[3], n[3];
+    for (int a = 0; a < 3; ++a) {
+        eu[a] = P10[a] - P00[a];
+        ev[a] = P01[a] - P00[a];
+    }
+    n[0] = eu[1] * ev[2] - eu[2] * ev[1];
+    n[1] = eu[2] * ev[0] - eu[0] * ev[2];
+    n[2] = eu[0] * ev[1] - eu[1] * ev[0];
+    const double eu2 = eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2];
+    const double ev2 = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+    double dn = 0.0;   /* (P00 - S) . n */
+    for (int a = 0; a < 3; ++a) dn += (P00[a] - S[a]) * n[a];
     for (int q = 0; q < 8; ++q) {
-        const double X = (q & 1) ? bh[0] : bl[0];
-        const double Y = (q & 2) ? bh[1] : bl[1];
-        const double Z = (q & 4) ? bh[2] : bl[2];
-        const double U = g->DSO - (X * c + Y * s);
-        if (U <= 0.0) return 0;
-        const double ud = g->DSD / U * (-X * s + Y * c);
-        const double vd = g->DSD / U * Z;
-        const double fu = (ud - g->ou) / g->du + 0.5 * (double)g->nu - 0.5;
-        const double fv = (vd - g->ov) / g->dv + 0.5 * (double)g->nv - 0.5;
+        const double X[3] = {(q & 1) ? bh[0] : bl[0], (q & 2) ? bh[1] : bl[1], (q & 4) ? bh[2] : bl[2]};
+        double xn = 0.0;
+        for (int a = 0; a < 3; ++a) xn += (X[a] - S[a]) * n[a];
+        /* the corner must lie beyond the source, on the detector's side */
+        if (!(xn / dn > 0.0)) return 0;
+        const double t = dn / xn;   /* S + t (X - S) lies on the detector plane */
+        double pu = 0.0, pv = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double d = S[a] + t * (X[a] - S[a]) - P00[a];
+            pu += d * eu[a];
+            pv += d * ev[a];
+        }
+        const double fu = pu / eu2, fv = pv / ev2;
         umin = fmin(umin, fu); umax = fmax(umax, fu);
         vmin = fmin(vmin, fv); vmax = fmax(vmax, fv);
     }
@@ -434,11 +545,11 @@ void orc_siddon_adjoint_voxels(const orc_geo* g, const double* angles, int64_t n
         double acc = 0.0;
         for (int64_t k = 0; k < nviews; ++k) {
             int64_t u0, u1, v0, v1;
-            if (!box_footprint(g, angles[k], bl, bh, &u0, &u1, &v0, &v1)) continue;
+            if (!box_footprint(g, angles, k, bl, bh, &u0, &u1, &v0, &v1)) continue;
             for (int64_t iv = v0; iv <= v1; ++iv)
                 for (int64_t iu = u0; iu <= u1; ++iu) {
                     double S[3], P[3];
-                    ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+                    ray_endpoints(g, angles, k, (double)iv, (double)iu, S, P);
                     const double w = box_chord(S, P, bl, bh);
                     if (w > 0.0) acc += w * proj[(k * g->nv + iv) * g->nu + iu];
                 }
@@ -467,11 +578,11 @@ void orc_interp_adjoint_voxels(const orc_geo* g, const double* angles, int64_t n
         double acc = 0.0;
         for (int64_t k = 0; k < nviews; ++k) {
             int64_t u0, u1, v0, v1;
-            if (!box_footprint(g, angles[k], bl, bh, &u0, &u1, &v0, &v1)) continue;
+            if (!box_footprint(g, angles, k, bl, bh, &u0, &u1, &v0, &v1)) continue;
             for (int64_t iv = v0; iv <= v1; ++iv)
                 for (int64_t iu = u0; iu <= u1; ++iu) {
                     double S[3], P[3];
-                    ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+                    ray_endpoints(g, angles, k, (double)iv, (double)iu, S, P);
                     interp_ray_t r;
                     if (!interp_setup(g, S, P, &r)) continue;
                     /* phi(. - j) vanishes outside the support box: only the
@@ -533,11 +644,11 @@ void orc_gradient_voxels(const orc_geo* g, int kind, const double* angles, int64
             double acc = 0.0;
             for (int64_t k = 0; k < nviews; ++k) {
                 int64_t u0, u1, v0, v1;
-                if (!box_footprint(g, angles[k], bl, bh, &u0, &u1, &v0, &v1)) continue;
+                if (!box_footprint(g, angles, k, bl, bh, &u0, &u1, &v0, &v1)) continue;
                 for (int64_t iv = v0; iv <= v1; ++iv)
                     for (int64_t iu = u0; iu <= u1; ++iu) {
                         double S[3], P[3];
-                        ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+                        ray_endpoints(g, angles, k, (double)iv, (double)iu, S, P);
                         double a_ij = 0.0;
                         if (kind == ORC_SIDDON) {
                             a_ij = box_chord(S, P, bl, bh);
@@ -580,7 +691,7 @@ void orc_dense_matrix(const orc_geo* g, int kind, const double* angles, int64_t 
     for (int64_t r = 0; r < nray; ++r) {
         const int64_t k = r / (g->nv * g->nu), iv = (r / g->nu) % g->nv, iu = r % g->nu;
         double S[3], P[3];
-        ray_endpoints(g, angles[k], (double)iv, (double)iu, S, P);
+        ray_endpoints(g, angles, k, (double)iv, (double)iu, S, P);
         interp_ray_t ir;
         const int has = kind == ORC_INTERP ? interp_setup(g, S, P, &ir) : 0;
         for (int64_t jz = 0; jz < n[2]; ++jz)

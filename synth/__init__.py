@@ -78,6 +78,59 @@ def circular_angles(n: int) -> np.ndarray:
     return 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
 
 
+@dataclasses.dataclass(frozen=True, eq=False)
+class Views:
+    """Per-projection geometry (the paper's geometric flexibility: Euler ZYZ
+    gantry angles, centre-of-rotation shift, in-place detector rotation, and
+    every parameter except the image and detector sizes settable per
+    projection).  Arrays over the views:
+      angles      (n, 3) z1, y1, z2 (rad), gantry R = Rz(z1) Ry(y1) Rz(z2);
+      DSO, DSD    (n,)   mm;
+      offOrigin   (n, 3) z, y, x (mm) volume centre;
+      offDetector (n, 2) v, u (mm), along the (rotated) detector axes;
+      COR         (n,)   mm, source-detector line shifted along the machine
+                         y axis (before the gantry rotation);
+      rotDetector (n, 3) roll, pitch, yaw (rad) of the detector about its
+                         centre: about its normal, its u axis, its v axis.
+    (z1, 0, 0) with the other fields from the Geometry is the circular orbit.
+    """
+    angles: np.ndarray
+    DSO: np.ndarray
+    DSD: np.ndarray
+    offOrigin: np.ndarray
+    offDetector: np.ndarray
+    COR: np.ndarray
+    rotDetector: np.ndarray
+
+    def __len__(self) -> int:
+        return int(self.angles.shape[0])
+
+    def __getitem__(self, idx) -> "Views":
+        return Views(*(np.atleast_1d(np.asarray(getattr(self, f.name)))[idx] if f.name in ("DSO", "DSD", "COR")
+                       else np.asarray(getattr(self, f.name))[idx] for f in dataclasses.fields(self)))
+
+
+def views(geo: Geometry, angles, **per_view) -> Views:
+    """Views from z1 angles (or (n, 3) ZYZ angles) with the Geometry's
+    scalar parameters, any of which may be overridden per view."""
+    a = np.asarray(angles, dtype=np.float64)
+    if a.ndim == 1:
+        a = np.stack([a, np.zeros_like(a), np.zeros_like(a)], axis=1)
+    n = a.shape[0]
+
+    def arr(name, default, width=None):
+        v = np.asarray(per_view.get(name, default), dtype=np.float64)
+        shape = (n,) if width is None else (n, width)
+        return np.ascontiguousarray(np.broadcast_to(v, shape))
+
+    unknown = set(per_view) - {"DSO", "DSD", "offOrigin", "offDetector", "COR", "rotDetector"}
+    if unknown:
+        raise ValueError(f"unknown per-view fields {sorted(unknown)}")
+    return Views(np.ascontiguousarray(a), arr("DSO", geo.DSO), arr("DSD", geo.DSD),
+                 arr("offOrigin", geo.offOrigin, 3), arr("offDetector", geo.offDetector, 2),
+                 arr("COR", 0.0), arr("rotDetector", (0.0, 0.0, 0.0), 3))
+
+
 # ---------------------------------------------------------------- workloads
 # Five synthetic workloads.  DSO/DSD are shared; sizes follow the cone-beam
 # experiment shapes (a 1024x768 detector like the clinical head scans).
