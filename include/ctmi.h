@@ -119,6 +119,37 @@ int ctmi_view_table(const ctmi_geometry* geo, const double* angles, int64_t nvie
  * success only. */
 int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nviews, ctmi_plan** out);
 
+/* Geometry of one projection for plans with per-view geometry (the paper's
+ * section on geometric flexibility and its geometry-parameter table: Euler
+ * ZYZ gantry angles, centre-of-rotation shift, in-place detector rotation,
+ * and every parameter except the image and detector sizes per projection).
+ * Machine frame before the gantry rotation: source (DSO, COR, 0), detector
+ * centre (DSO - DSD, COR, 0), detector axes u = (0, 1, 0), v = (0, 0, 1)
+ * (x points at the source).  The detector turns about its centre by
+ * Rx(roll) Ry(pitch) Rz(yaw); offDetector moves the pixel grid along the
+ * turned axes; the gantry turns everything about the origin by
+ * Rz(z1) Ry(y1) Rz(z2); offOrigin places the volume centre.  Angles in rad,
+ * lengths in mm; (z1, 0, 0) with zero COR and rotation is the circular orbit
+ * of ctmi_plan_create. */
+typedef struct {
+    double angles[3];      /* z1, y1, z2 */
+    double DSD, DSO;
+    double offOrigin[3];   /* z, y, x */
+    double offDetector[2]; /* v, u */
+    double COR;
+    double rotDetector[3]; /* roll (about the detector normal), pitch (about u), yaw (about v) */
+} ctmi_view;
+
+/* Create a plan from per-view geometry: `views` is a HOST array of nviews
+ * records; from `geo` only the sizes are used (nVoxel, dVoxel, nDetector,
+ * dDetector, accuracy).  Checks the sizes as ctmi_geometry_check, and per
+ * view finite values, 0 < DSO < DSD, and the volume's circumscribed sphere
+ * (grown by one voxel) in front of the source and on the source's side of
+ * the detector plane.  The projectors and their adjoints accept such plans;
+ * the FDK filter and backprojector (defined for the circular orbit) return
+ * CTMI_EUNSUPPORTED on them. */
+int ctmi_plan_create_views(const ctmi_geometry* geo, const ctmi_view* views, int64_t nviews, ctmi_plan** out);
+
 /* Destroy a plan; waits for the device, then frees the plan's table.  No
  * call using the plan may be in flight.  NULL is accepted. */
 int ctmi_plan_destroy(ctmi_plan* plan);

@@ -43,12 +43,35 @@ def geometry_struct(geo) -> CtmiGeometry:
     return g
 
 
+class CtmiView(ctypes.Structure):
+    _fields_ = [("angles", c_d * 3), ("DSD", c_d), ("DSO", c_d), ("offOrigin", c_d * 3), ("offDetector", c_d * 2),
+                ("COR", c_d), ("rotDetector", c_d * 3)]
+
+
+def view_structs(views):
+    """ctmi_view records from a per-view description: any object with
+    per-view arrays angles (n, 3) z1 y1 z2, DSO, DSD (n,), offOrigin (n, 3),
+    offDetector (n, 2), COR (n,), rotDetector (n, 3)."""
+    import numpy as np
+    a = np.asarray(views.angles, dtype=np.float64).reshape(-1, 3)
+    n = a.shape[0]
+    col = lambda name, w: np.broadcast_to(np.asarray(getattr(views, name), dtype=np.float64), (n,) if w == 1 else (n, w))
+    dso, dsd, cor = col("DSO", 1), col("DSD", 1), col("COR", 1)
+    oo, od, rd = col("offOrigin", 3), col("offDetector", 2), col("rotDetector", 3)
+    tab = (CtmiView * n)()
+    for k in range(n):
+        tab[k] = CtmiView((c_d * 3)(*a[k]), float(dsd[k]), float(dso[k]), (c_d * 3)(*oo[k]), (c_d * 2)(*od[k]),
+                          float(cor[k]), (c_d * 3)(*rd[k]))
+    return tab
+
+
 _SIGS = {
     "ctmi_last_error": (ctypes.c_char_p, []),
     "ctmi_version": (ctypes.c_char_p, []),
     "ctmi_geometry_check": (c_int, [c_p, c_p, c_i64]),
     "ctmi_view_table": (c_int, [c_p, c_p, c_i64, c_p]),
     "ctmi_plan_create": (c_int, [c_p, c_p, c_i64, ctypes.POINTER(c_p)]),
+    "ctmi_plan_create_views": (c_int, [c_p, c_p, c_i64, ctypes.POINTER(c_p)]),
     "ctmi_plan_destroy": (c_int, [c_p]),
     "ctmi_forward": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),
     "ctmi_backproject": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_f, c_p]),

@@ -39,55 +39,65 @@ int hip_fail(hipError_t e, const char* what)
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int check_geometry(const ctmi_geometry* g, const double* angles, int64_t nviews)
+// Sizes shared by every plan: counts, spacings, the interpolation step and
+// the index ranges the kernels rely on.
+int check_sizes(const ctmi_geometry* g, int64_t nviews)
 {
     if (!g) return fail(CTMI_EINVAL, "geometry is NULL");
     if (nviews < 1) return fail(CTMI_EINVAL, "nviews must be >= 1 (got %lld)", (long long)nviews);
-    if (!angles) return fail(CTMI_EINVAL, "angles is NULL");
-    if (!finite_pos(g->DSO) || !finite_pos(g->DSD)) return fail(CTMI_EINVAL, "DSO and DSD must be finite and > 0");
-    if (!(g->DSD > g->DSO)) return fail(CTMI_EINVAL, "DSD must exceed DSO");
     for (int a = 0; a < 3; ++a) {
         if (g->nVoxel[a] < 1) return fail(CTMI_EINVAL, "nVoxel[%d] must be >= 1", a);
         if (!finite_pos(g->dVoxel[a])) return fail(CTMI_EINVAL, "dVoxel[%d] must be finite and > 0", a);
-        if (!std::isfinite(g->offOrigin[a])) return fail(CTMI_EINVAL, "offOrigin[%d] is not finite", a);
-        if (!std::isfinite(g->rotDetector[a])) return fail(CTMI_EINVAL, "rotDetector[%d] is not finite", a);
     }
     for (int a = 0; a < 2; ++a) {
         if (g->nDetector[a] < 1) return fail(CTMI_EINVAL, "nDetector[%d] must be >= 1", a);
         if (!finite_pos(g->dDetector[a])) return fail(CTMI_EINVAL, "dDetector[%d] must be finite and > 0", a);
-        if (!std::isfinite(g->offDetector[a])) return fail(CTMI_EINVAL, "offDetector[%d] is not finite", a);
     }
     if (!finite_pos(g->accuracy)) return fail(CTMI_EINVAL, "accuracy must be finite and > 0");
-    if (!std::isfinite(g->COR)) return fail(CTMI_EINVAL, "COR is not finite");
-    for (int64_t k = 0; k < nviews; ++k)
-        if (!std::isfinite(angles[k])) return fail(CTMI_EINVAL, "angle %lld is not finite", (long long)k);
-    if (g->COR != 0.0) return fail(CTMI_EUNSUPPORTED, "COR != 0 is not modelled by this build");
-    if (g->rotDetector[0] != 0.0 || g->rotDetector[1] != 0.0 || g->rotDetector[2] != 0.0)
-        return fail(CTMI_EUNSUPPORTED, "rotDetector != 0 is not modelled by this build");
     const int64_t nz = g->nVoxel[0], ny = g->nVoxel[1], nx = g->nVoxel[2];
     if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 20)) return fail(CTMI_EOVERFLOW, "volume dimension too large");
     if ((double)nx * ny * nz >= 2147483648.0) return fail(CTMI_EOVERFLOW, "volume must hold < 2^31 voxels");
     const int64_t nv = g->nDetector[0], nu = g->nDetector[1];
     if (nu > 4096 || nv > (1 << 20)) return fail(CTMI_EOVERFLOW, "detector must have nu <= 4096");
     if (nviews > (1 << 24)) return fail(CTMI_EOVERFLOW, "too many views");
-    {
-        // the interpolated projector's samples of one ray inside the volume
-        // (its diagonal over the step) must stay below 2^15
-        const double hmin = std::fmin(g->dVoxel[0], std::fmin(g->dVoxel[1], g->dVoxel[2]));
-        const double diag = std::sqrt((double)nx * nx * g->dVoxel[2] * g->dVoxel[2] +
-                                      (double)ny * ny * g->dVoxel[1] * g->dVoxel[1] +
-                                      (double)nz * nz * g->dVoxel[0] * g->dVoxel[0]);
-        if (diag / (g->accuracy * hmin) + 8.0 >= 32768.0)
-            return fail(CTMI_EOVERFLOW, "more than 2^15 interpolation samples per ray: raise accuracy");
+    // the interpolated projector's samples of one ray inside the volume (its
+    // diagonal over the step) must stay below 2^15
+    const double hmin = std::fmin(g->dVoxel[0], std::fmin(g->dVoxel[1], g->dVoxel[2]));
+    const double diag = std::sqrt((double)nx * nx * g->dVoxel[2] * g->dVoxel[2] +
+                                  (double)ny * ny * g->dVoxel[1] * g->dVoxel[1] +
+                                  (double)nz * nz * g->dVoxel[0] * g->dVoxel[0]);
+    if (diag / (g->accuracy * hmin) + 8.0 >= 32768.0)
+        return fail(CTMI_EOVERFLOW, "more than 2^15 interpolation samples per ray: raise accuracy");
+    return CTMI_OK;
+}
+
+int check_geometry(const ctmi_geometry* g, const double* angles, int64_t nviews)
+{
+    int rc;
+    if ((rc = check_sizes(g, nviews))) return rc;
+    if (!angles) return fail(CTMI_EINVAL, "angles is NULL");
+    if (!finite_pos(g->DSO) || !finite_pos(g->DSD)) return fail(CTMI_EINVAL, "DSO and DSD must be finite and > 0");
+    if (!(g->DSD > g->DSO)) return fail(CTMI_EINVAL, "DSD must exceed DSO");
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(g->offOrigin[a])) return fail(CTMI_EINVAL, "offOrigin[%d] is not finite", a);
+        if (!std::isfinite(g->rotDetector[a])) return fail(CTMI_EINVAL, "rotDetector[%d] is not finite", a);
     }
+    for (int a = 0; a < 2; ++a)
+        if (!std::isfinite(g->offDetector[a])) return fail(CTMI_EINVAL, "offDetector[%d] is not finite", a);
+    if (!std::isfinite(g->COR)) return fail(CTMI_EINVAL, "COR is not finite");
+    for (int64_t k = 0; k < nviews; ++k)
+        if (!std::isfinite(angles[k])) return fail(CTMI_EINVAL, "angle %lld is not finite", (long long)k);
+    if (g->COR != 0.0)
+        return fail(CTMI_EUNSUPPORTED, "COR != 0 needs per-view geometry (ctmi_plan_create_views)");
+    if (g->rotDetector[0] != 0.0 || g->rotDetector[1] != 0.0 || g->rotDetector[2] != 0.0)
+        return fail(CTMI_EUNSUPPORTED, "rotDetector != 0 needs per-view geometry (ctmi_plan_create_views)");
     // the volume's circumscribed sphere, grown by one voxel, must lie strictly
     // between the source and the detector plane for every view
-    double half2 = 0.0, off2 = 0.0, dmax = 0.0;
+    double half2 = 0.0, off2 = 0.0;
     for (int a = 0; a < 3; ++a) {
         const double h = 0.5 * (double)g->nVoxel[a] * g->dVoxel[a] + g->dVoxel[a];
         half2 += h * h;
         off2 += g->offOrigin[a] * g->offOrigin[a];
-        dmax = std::fmax(dmax, g->dVoxel[a]);
     }
     const double R = std::sqrt(half2) + std::sqrt(off2);
     if (!(g->DSO > R)) return fail(CTMI_EINVAL, "the source passes within the volume (DSO %.6g <= radius %.6g)", g->DSO, R);
@@ -151,6 +161,162 @@ void view_table(const ctmi_geometry* g, const double* angles, int64_t nviews, Vi
             o.MW[a] = (float)MW[a];
         }
     }
+}
+
+// 3x3 rotations (row-major) and products for the per-view frames.
+struct Rot {
+    double m[3][3];
+};
+
+Rot rot_axis(int axis, double a)
+{
+    const double c = std::cos(a), s = std::sin(a);
+    Rot r{};
+    const int i = (axis + 1) % 3, j = (axis + 2) % 3;   // the plane the rotation acts in
+    r.m[axis][axis] = 1.0;
+    r.m[i][i] = c;
+    r.m[i][j] = -s;
+    r.m[j][i] = s;
+    r.m[j][j] = c;
+    return r;
+}
+
+Rot mul(const Rot& A, const Rot& B)
+{
+    Rot C{};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) C.m[i][j] += A.m[i][k] * B.m[k][j];
+    return C;
+}
+
+void apply(const Rot& R, const double v[3], double out[3])
+{
+    for (int i = 0; i < 3; ++i) out[i] = R.m[i][0] * v[0] + R.m[i][1] * v[1] + R.m[i][2] * v[2];
+}
+
+// World frame of one view, relative to its volume centre: source S, centre
+// of pixel (0, 0) P00, unit detector axes eu, ev (mm).
+void view_frame(const ctmi_geometry* g, const ctmi_view& w, double S[3], double P00[3], double eu[3], double ev[3])
+{
+    // gantry Rz(z1) Ry(y1) Rz(z2); detector Rx(roll) Ry(pitch) Rz(yaw) about
+    // its centre, in the machine frame (x towards the source, u = y, v = z)
+    const Rot G = mul(rot_axis(2, w.angles[0]), mul(rot_axis(1, w.angles[1]), rot_axis(2, w.angles[2])));
+    const Rot Dt = mul(rot_axis(0, w.rotDetector[0]), mul(rot_axis(1, w.rotDetector[1]), rot_axis(2, w.rotDetector[2])));
+    const Rot GD = mul(G, Dt);
+    const double s0[3] = {w.DSO, w.COR, 0.0}, d0[3] = {w.DSO - w.DSD, w.COR, 0.0};
+    const double ux[3] = {0.0, 1.0, 0.0}, vx[3] = {0.0, 0.0, 1.0};
+    double D[3];
+    apply(G, s0, S);
+    apply(G, d0, D);
+    apply(GD, ux, eu);
+    apply(GD, vx, ev);
+    const double o[3] = {w.offOrigin[2], w.offOrigin[1], w.offOrigin[0]};   // x, y, z
+    const double nu = (double)g->nDetector[1], nv = (double)g->nDetector[0];
+    const double u0 = (0.5 - 0.5 * nu) * g->dDetector[1] + w.offDetector[1];
+    const double v0 = (0.5 - 0.5 * nv) * g->dDetector[0] + w.offDetector[0];
+    for (int a = 0; a < 3; ++a) {
+        S[a] -= o[a];
+        P00[a] = D[a] - o[a] + u0 * eu[a] + v0 * ev[a];
+    }
+}
+
+// Per-view table for general frames.  Rays as in view_table (voxel-cell
+// coordinates); the 3x4 rows give (fu W, fv W, W) from voxel-centre indices
+// with W = 1 on the detector plane and 0 on the source's parallel plane
+// (only fu, fv = ratios are used: detector footprints).
+void view_table_general(const ctmi_geometry* g, const ctmi_view* views, int64_t nviews, ViewGeo* out,
+                        ctmi::ViewGeo64* out64)
+{
+    const double h[3] = {g->dVoxel[2], g->dVoxel[1], g->dVoxel[0]};
+    const double lo[3] = {-0.5 * (double)g->nVoxel[2] * h[0], -0.5 * (double)g->nVoxel[1] * h[1],
+                          -0.5 * (double)g->nVoxel[0] * h[2]};
+    const double du = g->dDetector[1], dv = g->dDetector[0];
+    for (int64_t k = 0; k < nviews; ++k) {
+        double S[3], P00[3], eu[3], ev[3];
+        view_frame(g, views[k], S, P00, eu, ev);
+        ViewGeo& o = out[k];
+        std::memset(&o, 0, sizeof o);
+        ctmi::ViewGeo64& o64 = out64[k];
+        std::memset(&o64, 0, sizeof o64);
+        for (int a = 0; a < 3; ++a) {
+            o64.S[a] = (S[a] - lo[a]) / h[a];
+            o64.P00[a] = (P00[a] - lo[a]) / h[a];
+            o64.DU[a] = du * eu[a] / h[a];
+            o64.DV[a] = dv * ev[a] / h[a];
+            o.S[a] = (float)o64.S[a];
+            o.P00[a] = (float)o64.P00[a];
+            o.DU[a] = (float)o64.DU[a];
+            o.DV[a] = (float)o64.DV[a];
+        }
+        // central projection of world point X onto the detector plane:
+        // W = (X - S).n / (P00 - S).n, then (fu W, fv W) = ((S - P00) W + X - S).(eu / du, ev / dv)
+        const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2], eu[0] * ev[1] - eu[1] * ev[0]};
+        double den = 0.0, spu = 0.0, spv = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            den += (P00[a] - S[a]) * n[a];
+            spu += (S[a] - P00[a]) * eu[a];
+            spv += (S[a] - P00[a]) * ev[a];
+        }
+        // X = lo + (c + 1/2) h; X - S = (lo + h/2 - S) + c h
+        double MW[4] = {0.0, 0.0, 0.0, 0.0}, MU[4] = {0.0, 0.0, 0.0, 0.0}, MV[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; ++a) {
+            MW[a] = h[a] * n[a] / den;
+            MU[a] = (spu * MW[a] + h[a] * eu[a]) / du;
+            MV[a] = (spv * MW[a] + h[a] * ev[a]) / dv;
+            const double x0 = lo[a] + 0.5 * h[a] - S[a];
+            MW[3] += x0 * n[a] / den;
+        }
+        for (int a = 0; a < 3; ++a) {
+            const double x0 = lo[a] + 0.5 * h[a] - S[a];
+            MU[3] += x0 * eu[a] / du;
+            MV[3] += x0 * ev[a] / dv;
+        }
+        MU[3] += spu * MW[3] / du;
+        MV[3] += spv * MW[3] / dv;
+        for (int a = 0; a < 4; ++a) {
+            o.MU[a] = (float)MU[a];
+            o.MV[a] = (float)MV[a];
+            o.MW[a] = (float)MW[a];
+        }
+    }
+}
+
+// Per-view checks: finite values, the volume's circumscribed sphere (grown by
+// one voxel) in front of the source and on the source's side of the
+// detector plane, by more than its radius.
+int check_views(const ctmi_geometry* g, const ctmi_view* views, int64_t nviews)
+{
+    double half2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double hh = 0.5 * (double)g->nVoxel[a] * g->dVoxel[a] + g->dVoxel[a];
+        half2 += hh * hh;
+    }
+    const double R = std::sqrt(half2);
+    for (int64_t k = 0; k < nviews; ++k) {
+        const ctmi_view& w = views[k];
+        bool ok = std::isfinite(w.DSO) && std::isfinite(w.DSD) && std::isfinite(w.COR);
+        for (int a = 0; a < 3; ++a)
+            ok = ok && std::isfinite(w.angles[a]) && std::isfinite(w.offOrigin[a]) && std::isfinite(w.rotDetector[a]);
+        ok = ok && std::isfinite(w.offDetector[0]) && std::isfinite(w.offDetector[1]);
+        if (!ok) return fail(CTMI_EINVAL, "view %lld has a non-finite parameter", (long long)k);
+        if (!(w.DSO > 0.0) || !(w.DSD > w.DSO)) return fail(CTMI_EINVAL, "view %lld: need 0 < DSO < DSD", (long long)k);
+        double S[3], P00[3], eu[3], ev[3];
+        view_frame(g, w, S, P00, eu, ev);
+        const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2], eu[0] * ev[1] - eu[1] * ev[0]};
+        // orient n from the detector towards the source
+        double sd = 0.0;
+        for (int a = 0; a < 3; ++a) sd += (S[a] - P00[a]) * n[a];
+        const double sg = sd > 0.0 ? 1.0 : -1.0;
+        double cs = 0.0, cd = 0.0;   // volume centre (origin) to the source's and the detector's planes
+        for (int a = 0; a < 3; ++a) {
+            cs += (S[a] - 0.0) * n[a] * sg;
+            cd += (0.0 - P00[a]) * n[a] * sg;
+        }
+        if (!(cs > R)) return fail(CTMI_EINVAL, "view %lld: the source passes within the volume", (long long)k);
+        if (!(cd > R)) return fail(CTMI_EINVAL, "view %lld: the detector cuts the volume", (long long)k);
+    }
+    return CTMI_OK;
 }
 
 int bitrev(int x, int bits)
@@ -253,11 +419,9 @@ int ctmi_view_table(const ctmi_geometry* geo, const double* angles, int64_t nvie
     return CTMI_OK;
 }
 
-int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nviews, ctmi_plan** out)
+static int create_plan(const ctmi_geometry* geo, const double* angles, const ctmi_view* views, int64_t nviews,
+                       ctmi_plan** out)
 {
-    if (!out) return fail(CTMI_EINVAL, "out is NULL");
-    int rc = check_geometry(geo, angles, nviews);
-    if (rc) return rc;
     ctmi_plan* p = new (std::nothrow) ctmi_plan();
     if (!p) return fail(CTMI_EINVAL, "out of host memory");
     p->geo = *geo;
@@ -299,7 +463,11 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
 
     std::vector<ViewGeo> t(nviews);
     std::vector<ctmi::ViewGeo64> t64(nviews);
-    view_table(geo, angles, nviews, t.data(), t64.data());
+    p->circular = views == nullptr;
+    if (views)
+        view_table_general(geo, views, nviews, t.data(), t64.data());
+    else
+        view_table(geo, angles, nviews, t.data(), t64.data());
     std::vector<float> Hbr, tw;
     ramp_tables(geo, L, logL, Hbr, tw);
 
@@ -339,6 +507,26 @@ int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nvi
     return CTMI_OK;
 }
 
+int ctmi_plan_create(const ctmi_geometry* geo, const double* angles, int64_t nviews, ctmi_plan** out)
+{
+    if (!out) return fail(CTMI_EINVAL, "out is NULL");
+    int rc = check_geometry(geo, angles, nviews);
+    if (rc) return rc;
+    return create_plan(geo, angles, nullptr, nviews, out);
+}
+
+int ctmi_plan_create_views(const ctmi_geometry* geo, const ctmi_view* views, int64_t nviews, ctmi_plan** out)
+{
+    if (!out) return fail(CTMI_EINVAL, "out is NULL");
+    if (!views) return fail(CTMI_EINVAL, "views is NULL");
+    if (!geo) return fail(CTMI_EINVAL, "geometry is NULL");
+    if (nviews < 1) return fail(CTMI_EINVAL, "nviews must be >= 1 (got %lld)", (long long)nviews);
+    int rc;
+    if ((rc = check_sizes(geo, nviews))) return rc;
+    if ((rc = check_views(geo, views, nviews))) return rc;
+    return create_plan(geo, nullptr, views, nviews, out);
+}
+
 int ctmi_plan_destroy(ctmi_plan* plan)
 {
     if (!plan) return CTMI_OK;
@@ -373,6 +561,8 @@ int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vo
     if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
     if (bp != CTMI_BP_SIDDON && bp != CTMI_BP_INTERP && bp != CTMI_BP_FDK)
         return fail(CTMI_EINVAL, "unknown backprojector %d", bp);
+    if (bp == CTMI_BP_FDK && !plan->circular)
+        return fail(CTMI_EUNSUPPORTED, "the FDK backprojector needs a circular-orbit plan");
     if (!std::isfinite(beta)) return fail(CTMI_EINVAL, "beta is not finite");
     if ((rc = check_ptr(vol, "vol")) || (nviews > 0 && (rc = check_ptr(proj, "proj"))) ||
         (rc = check_device(plan)))
@@ -395,6 +585,7 @@ int ctmi_fdk_filter(const ctmi_plan* plan, int wang, const float* proj, float* o
 {
     int rc;
     if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
+    if (!plan->circular) return fail(CTMI_EUNSUPPORTED, "the FDK filter needs a circular-orbit plan");
     if (nviews == 0) return CTMI_OK;
     if ((rc = check_ptr(proj, "proj")) || (rc = check_ptr(out, "out")) || (rc = check_device(plan))) return rc;
     if (wang && plan->geo.offDetector[1] != 0.0 &&

@@ -63,6 +63,7 @@ struct DetDims {
 struct Plan {
     ctmi_geometry geo;
     int64_t nviews;
+    bool circular;        // every view is the circular default (FDK is defined for it)
     int device;
     ViewGeo* d_views;     // [nviews]
     ViewGeo64* d_views64; // [nviews]

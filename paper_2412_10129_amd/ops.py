@@ -57,17 +57,29 @@ class Plan:
     """A cone-beam geometry and its angles, resident on one GPU."""
 
     def __init__(self, geo, angles, device=None):
+        """angles: z1 angles of a circular orbit (rad), or a per-view
+        geometry description (an object with per-view arrays angles (n, 3),
+        DSO, DSD, offOrigin, offDetector, COR, rotDetector; the FDK pieces
+        then refuse the plan)."""
         self.geo = geo
-        self.angles = np.ascontiguousarray(angles, dtype=np.float64)
-        self.nviews = len(self.angles)
+        self.views = angles if hasattr(angles, "rotDetector") else None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.vol_shape = tuple(int(v) for v in geo.nVoxel)
         self.det_shape = tuple(int(v) for v in geo.nDetector)
         g = L.geometry_struct(geo)
         h = ctypes.c_void_p()
-        with torch.cuda.device(self.device):
-            L.check(L.lib().ctmi_plan_create(ctypes.byref(g), self.angles.ctypes.data_as(ctypes.c_void_p),
-                                             self.nviews, ctypes.byref(h)))
+        if self.views is None:
+            self.angles = np.ascontiguousarray(angles, dtype=np.float64)
+            self.nviews = len(self.angles)
+            with torch.cuda.device(self.device):
+                L.check(L.lib().ctmi_plan_create(ctypes.byref(g), self.angles.ctypes.data_as(ctypes.c_void_p),
+                                                 self.nviews, ctypes.byref(h)))
+        else:
+            tab = L.view_structs(self.views)
+            self.nviews = len(tab)
+            self.angles = np.ascontiguousarray(np.asarray(self.views.angles, dtype=np.float64).reshape(-1, 3)[:, 0])
+            with torch.cuda.device(self.device):
+                L.check(L.lib().ctmi_plan_create_views(ctypes.byref(g), tab, self.nviews, ctypes.byref(h)))
         self._h = h
         self._ws = torch.empty(L.lib().ctmi_reduce_workspace_bytes(0) // 8, dtype=torch.float64, device=self.device)
 
