@@ -368,6 +368,30 @@ def main():
             breakdown[name] = ent
             print(f"[bench] {name}: {ent}", flush=True)
         del xs, bps
+        # the projectors under per-view geometry at the same size: orbit
+        # tilted by 0.2 rad, 1.5 mm centre-of-rotation shift, detector turned
+        # by (0.02, 0.01, -0.015) rad
+        import types
+        ang = np.asarray(plan.angles, dtype=np.float64)
+        nv_ = len(ang)
+        gviews = types.SimpleNamespace(
+            angles=np.stack([ang, np.full(nv_, 0.2), np.zeros(nv_)], axis=1), DSO=np.full(nv_, geo.DSO),
+            DSD=np.full(nv_, geo.DSD), offOrigin=np.zeros((nv_, 3)), offDetector=np.zeros((nv_, 2)),
+            COR=np.full(nv_, 1.5), rotDetector=np.tile([0.02, 0.01, -0.015], (nv_, 1)))
+        gplan = P.Plan(geo, gviews, dev)
+        for name, fn in (("interp_fwd_general", lambda: gplan.forward(x, out=q, kind="interp")),
+                         ("interp_bwd_general", lambda: gplan.backproject(b, out=s, kind="interp"))):
+            fn()
+            ea = torch.cuda.Event(enable_timing=True)
+            eb = torch.cuda.Event(enable_timing=True)
+            ea.record(stream)
+            fn()
+            eb.record(stream)
+            torch.cuda.synchronize()
+            t = ea.elapsed_time(eb)
+            breakdown[name] = {"ms": round(t, 3), "updates/s": float(f"{upd / (t / 1e3):.4g}")}
+            print(f"[bench] {name}: {breakdown[name]}", flush=True)
+        del gplan
         for name, make, it in (("mlem_iter", lambda: AL.OSEM(plan, None, kind), None),
                                ("os_asd_pocs_iter", lambda: AL.ASDPOCS(plan, 20, kind), None)):
             solver = make()
