@@ -46,7 +46,7 @@ namespace {
 #define CTMI_BWD_SID_CELLS 4
 #endif
 #ifndef CTMI_BWD_INT_SAMPLES
-#define CTMI_BWD_INT_SAMPLES 4
+#define CTMI_BWD_INT_SAMPLES 6
 #endif
 constexpr int BX = 16, BY = 16, BZ = CTMI_BWD_BZ;   // brick (voxels)
 constexpr int NB = BX * BY * BZ;
