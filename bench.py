@@ -194,9 +194,10 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", metavar="DB",
                     help="only print markdown tables of a rocprofv3 results database and exit")
+    ap.add_argument("--top", type=int, default=12, help="kernels listed by --profile-summary")
     args = ap.parse_args()
     if args.profile_summary:
-        print(profile_summary(args.profile_summary))
+        print(profile_summary(args.profile_summary, top=args.top))
         return
     if args.copy_calibration:
         import torch
