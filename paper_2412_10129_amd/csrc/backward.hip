@@ -140,6 +140,9 @@ __device__ __forceinline__ int round_pixel(int p0)
 #ifndef CTMI_BWD_SPREAD
 #define CTMI_BWD_SPREAD 1
 #endif
+#ifndef CTMI_BWD_XCD
+#define CTMI_BWD_XCD 0
+#endif
 #ifndef CTMI_BWD_SID_SPREAD
 #define CTMI_BWD_SID_SPREAD 0
 #endif
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int i = 0; i < OWN; ++i) own[i] = 0.0f;
     int bx, by, bz;
-    brick_origin(m, blockIdx.x, bx, by, bz);
+    brick_origin(m, (int)(CTMI_BWD_XCD ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x), bx, by, bz);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
     const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
     const float lo[3] = {x0 - 0.5f, y0 - 0.5f, z0 - 0.5f};   // cell box in voxel-centre coordinates
@@ -636,7 +639,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int i = 0; i < NH; ++i) hown[i] = 0.0f;
     int bx, by, bz;
-    brick_origin(m, blockIdx.x, bx, by, bz);
+    brick_origin(m, (int)(CTMI_BWD_XCD ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x), bx, by, bz);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
     const int x1 = min(x0 + BX, v.nx), y1 = min(y0 + BY, v.ny), z1 = min(z0 + BZ, v.nz);
     // the brick takes samples whose lower corner lies in [x0, x1) (from -1

@@ -290,6 +290,17 @@ __device__ __forceinline__ void siddon_ray(const ViewGeo64& g, int iu, int iv, c
     a_hi = (float)(1.0 - t0);
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup i to XCD
+// i mod 8), and each XCD has its own L2.  This renumbering gives every XCD
+// one contiguous run of the logical block order, so blocks that read the
+// same data run under the same L2.  A bijection on [0, n).
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t n)
+{
+    const int64_t per = n / 8, rem = n % 8;
+    const int64_t x = b % 8, i = b / 8;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
 // --- interpolated ----------------------------------------------------------
 // Samples of the ray in voxel-centre coordinates: sample k is at
 // base + (k - kc) st, kc the middle sample of k0..k1, the samples inside the

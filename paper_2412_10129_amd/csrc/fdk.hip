@@ -14,6 +14,9 @@ namespace {
 // On a circular orbit W and fu do not depend on z, so per view a thread
 // computes one reciprocal and then walks its ZC voxels along v.
 constexpr int FDK_TX = 32, FDK_TY = 8, FDK_ZC = 8;
+#ifndef CTMI_FDK_XCD
+#define CTMI_FDK_XCD 0
+#endif
 
 __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __restrict__ proj,
                                                                  float* __restrict__ vol,
@@ -21,7 +24,7 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
                                                                  int nviews, VolDims v, DetDims det, int nbx,
                                                                  int nby, float beta)
 {
-    const int b = blockIdx.x;
+    const int b = CTMI_FDK_XCD ? (int)xcd_contiguous(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int ix = bx * FDK_TX + (int)(threadIdx.x % FDK_TX);
     const int iy = by * FDK_TY + (int)(threadIdx.x / FDK_TX);

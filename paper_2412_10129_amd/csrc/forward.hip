@@ -67,13 +67,47 @@ struct Box {
     int e[3];
 };
 
+#ifndef CTMI_FWD_XCD
+#define CTMI_FWD_XCD 1
+#endif
+#ifndef CTMI_FWD_ORDER
+#define CTMI_FWD_ORDER 1
+#endif
+#ifndef CTMI_FWD_VG
+#define CTMI_FWD_VG 16
+#endif
+
+// With CTMI_FWD_XCD each XCD runs a contiguous run of the tile order, so
+// tiles that stage overlapping volume boxes (neighbouring tiles of nearby
+// views) share an L2 (A 640 -> 582 ms, Siddon 690 -> 592 ms at 512^3 x 720).
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t nblocks)
+{
+    return CTMI_FWD_XCD ? xcd_contiguous(b, nblocks) : b;
+}
+
 __device__ __forceinline__ void tile_of_block(const TileMap& m, int64_t b, int& view, int& tu0, int& tv0)
 {
-    const int64_t per_row = m.nviews * m.tiles_u;
-    const int tv = (int)(b / per_row);
-    const int64_t rem = b - (int64_t)tv * per_row;
-    view = (int)(rem / m.tiles_u);
-    const int tu = (int)(rem - (int64_t)view * m.tiles_u);
+    b = xcd_order(b, (int64_t)m.tiles_u * m.tiles_v * m.nviews);
+    int tu, tv;
+    if (CTMI_FWD_ORDER == 0) {
+        // (tile row, view, tile column)
+        const int64_t per_row = m.nviews * m.tiles_u;
+        tv = (int)(b / per_row);
+        const int64_t rem = b - (int64_t)tv * per_row;
+        view = (int)(rem / m.tiles_u);
+        tu = (int)(rem - (int64_t)view * m.tiles_u);
+    } else {
+        // (tile row, groups of VG views, tile column, view in group)
+        const int64_t per_row = m.nviews * m.tiles_u;
+        tv = (int)(b / per_row);
+        int64_t rem = b - (int64_t)tv * per_row;
+        const int64_t gsz = (int64_t)CTMI_FWD_VG * m.tiles_u;
+        const int64_t g = rem / gsz;
+        rem -= g * gsz;
+        const int64_t nvg = min((int64_t)CTMI_FWD_VG, m.nviews - g * CTMI_FWD_VG);   // views in this group
+        tu = (int)(rem / nvg);
+        view = (int)(g * CTMI_FWD_VG + (rem - (int64_t)tu * nvg));
+    }
     tu0 = tu * TU;
     tv0 = tv * TV;
 }
