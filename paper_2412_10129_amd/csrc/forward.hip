@@ -36,7 +36,7 @@ namespace {
 #define CTMI_FWD_TV 16
 #endif
 #ifndef CTMI_FWD_SLAB
-#define CTMI_FWD_SLAB 8
+#define CTMI_FWD_SLAB 10
 #endif
 #ifndef CTMI_FWD_BOXCAP
 #define CTMI_FWD_BOXCAP 6144
