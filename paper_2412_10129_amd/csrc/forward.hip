@@ -1,7 +1,7 @@
 // Forward projectors A (the linear model A x = b of section 2.1): one thread
 // per detector pixel, projection-major ray tiles, LDS-staged volume slabs.
 //
-// A workgroup of 256 threads owns a 32x8 pixel tile of one view.  The tile's
+// A workgroup of 256 threads owns a 16x16 pixel tile of one view.  The tile's
 // rays run mostly along one axis (the dominant axis of the tile's central
 // ray); the volume is cut into slabs of SLAB cells across that axis and the
 // workgroup visits the slabs in the direction of travel.  For each slab it
@@ -13,9 +13,11 @@
 // box (box clipped to the LDS capacity, rounding at the box edge) reads them
 // from global memory, so the result never depends on the box estimate.
 //
-// Blocks are ordered (tile row, view, tile column): the workgroups in flight
-// share one detector row band, hence one z-slab of the volume, across many
-// views.
+// Blocks are ordered (tile row, groups of 16 views, tile column, view in
+// group), and renumbered so that each XCD runs a contiguous run of that
+// order: the workgroups in flight on one XCD share one detector row band,
+// hence one z-band of the volume, and stage overlapping boxes for nearby
+// views under one L2.
 //
 // The interpolated projector stages its boxes one slab ahead: the next
 // slab's first 2048 box elements are loaded into registers while the
