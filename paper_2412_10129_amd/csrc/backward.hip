@@ -39,16 +39,13 @@ namespace ctmi {
 
 namespace {
 
-#ifndef CTMI_BWD_BZ
-#define CTMI_BWD_BZ 8
-#endif
 #ifndef CTMI_BWD_SID_CELLS
 #define CTMI_BWD_SID_CELLS 4
 #endif
 #ifndef CTMI_BWD_INT_SAMPLES
 #define CTMI_BWD_INT_SAMPLES 6
 #endif
-constexpr int BX = 16, BY = 16, BZ = CTMI_BWD_BZ;   // brick (voxels)
+constexpr int BX = CTMI_BWD_BX, BY = CTMI_BWD_BY, BZ = CTMI_BWD_BZ;   // brick (voxels)
 constexpr int NB = BX * BY * BZ;
 constexpr int OWN = NB / 256;                     // voxels owned per thread
 typedef unsigned long long u64;
@@ -467,9 +464,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const float astart = q == 0 ? t_a0[r] : plane_alpha(ad, (float)(cfirst + (ad.step < 0)));
                 const float aend = (q * SID_CELLS + SID_CELLS >= nc) ? t_a1[r]
                                                                      : plane_alpha(ad, (float)(clast + (ad.step > 0)));
-                int ix = entry_cell(S[0], d[0], astart, ax.step, x0, x1);
-                int iy = entry_cell(S[1], d[1], astart, ay.step, y0, y1);
-                int iz = entry_cell(S[2], d[2], astart, az.step, z0, z1);
+                int ix = ordered_cell(ax, S[0], d[0], astart, x0, x1);
+                int iy = ordered_cell(ay, S[1], d[1], astart, y0, y1);
+                int iz = ordered_cell(az, S[2], d[2], astart, z0, z1);
                 if (dom == 0) ix = cfirst;
                 else if (dom == 1) iy = cfirst;
                 else iz = cfirst;
@@ -581,7 +578,10 @@ __device__ __forceinline__ void flush_shell(Acc* acc, float inv, float hown[NH])
 // neighbouring lanes) hold pixels far apart on the detector.  Item -> slot
 // lookups go through a 16-bit map for the first IMAPCAP items of a round.
 constexpr int RPT = 2, RAYS = 256 * RPT;
-constexpr int IMAPCAP = 4096;
+#ifndef CTMI_BWD_IMAPCAP
+#define CTMI_BWD_IMAPCAP 4096
+#endif
+constexpr int IMAPCAP = CTMI_BWD_IMAPCAP;
 static_assert(RAYS == 512, "slot permutation is a 9-bit reversal");
 
 __device__ __forceinline__ int slot_pixel(int s)
@@ -614,7 +614,10 @@ __device__ __forceinline__ int wave_scan(int x)
     return x;
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
+#ifndef CTMI_BWD_WAVES
+#define CTMI_BWD_WAVES 4
+#endif
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_BWD_WAVES, 8))) k_backward_interp(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
                                                          const ViewGeo64* __restrict__ tab64, int view0, int nviews,
                                                          VolDims v, DetDims det, BrickMap m, float beta, float ds,
@@ -681,9 +684,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     if (interp_ray(tab64[view0 + k + gv], iu, iv, v, ds, inv_ds, ray)) {
                         // samples (relative to the anchor kc) inside the brick's
                         // box, widened by 1e-3 of a sample against the
-                        // reciprocal's rounding (a sample outside the box adds
-                        // nothing: its weights are zeroed below)
-                        float kmin = -CTMI_INF, kmax = CTMI_INF;
+                        // reciprocal's rounding, and by the samples within
+                        // 2^-22 |face| of a face (|face| <= wface): a position
+                        // that close may round onto either side of it, and for
+                        // a ray nearly parallel to the face that span holds
+                        // many samples (the smallest nonzero step bounds it on
+                        // every axis).  A sample outside the box adds nothing
+                        // (its weights are zeroed below), so widening only
+                        // costs work, while a sample missed here would be lost.
+                        float kmin = -CTMI_INF, kmax = CTMI_INF, imax = 0.0f;
                         bool inside = true;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -692,13 +701,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                                 const float ka = (lo[a] - ray.base[a]) * ia, kb = (hi[a] - ray.base[a]) * ia;
                                 kmin = fmaxf(kmin, fminf(ka, kb));
                                 kmax = fminf(kmax, fmaxf(ka, kb));
+                                imax = fmaxf(imax, fabsf(ia));
                             } else {
-                                inside &= ray.base[a] > lo[a] && ray.base[a] < hi[a];
+                                // constant coordinate: the loop's own test
+                                const float f = __builtin_floorf(ray.base[a]);
+                                inside &= f >= lo[a] && f <= hi[a] - 1.0f;
                             }
                         }
-                        if (inside && kmin < kmax + 2e-3f) {
-                            const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin - 1e-3f));
-                            const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax + 1e-3f));
+                        // (capped at 2^16 samples, more than a ray holds, so
+                        // that the sample indices below stay in int range)
+                        const float wface = 0x1p-22f * fmaxf(hi[0], fmaxf(hi[1], hi[2]));
+                        const float wk = fminf(__builtin_fmaf(wface, imax, 1e-3f), 65536.0f);
+                        if (inside && kmin < kmax + 2.0f * wk) {
+                            const int ks = max(ray.k0, ray.kc + (int)__builtin_ceilf(kmin - wk));
+                            const int ke = min(ray.k1, ray.kc + (int)__builtin_floorf(kmax + wk));
                             const int n = ke - ks + 1;
                             if (n > 0 && n < 65536) {
                                 cnt[h] = (n + INT_SAMPLES - 1) / INT_SAMPLES;

@@ -480,8 +480,9 @@ static int create_plan(const ctmi_geometry* geo, const double* angles, const ctm
     const size_t t64b = sizeof(ctmi::ViewGeo64) * (size_t)nviews;
     const size_t hb = sizeof(float) * (size_t)L;
     const size_t wb = sizeof(float) * (size_t)L;  // L/2 float2
-    // upper shells of the interpolated adjoint's 16x16x8 voxel bricks
-    const size_t nbricks = (size_t)((p->vol.nx + 15) / 16) * ((p->vol.ny + 15) / 16) * ((p->vol.nz + 7) / 8);
+    // upper shells of the interpolated adjoint's voxel bricks
+    const size_t nbricks = (size_t)((p->vol.nx + CTMI_BWD_BX - 1) / CTMI_BWD_BX) *
+                           ((p->vol.ny + CTMI_BWD_BY - 1) / CTMI_BWD_BY) * ((p->vol.nz + CTMI_BWD_BZ - 1) / CTMI_BWD_BZ);
     const size_t sb = sizeof(float) * nbricks * CTMI_HALO_SLOTS;
     const size_t sof = (tb + t64b + hb + wb + 255) / 256 * 256;
     char* mem = nullptr;

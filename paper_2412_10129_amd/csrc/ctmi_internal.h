@@ -47,8 +47,20 @@ struct ViewGeo64 {
 };
 static_assert(sizeof(ViewGeo64) == 128, "FP64 view table row must be 128 bytes");
 
-// Cells in the upper shell of one 16x16x8 adjoint brick (faces x, y, z).
-#define CTMI_HALO_SLOTS (17 * 9 + 16 * 9 + 16 * 16)
+// Voxel bricks of the matched adjoints (x, y, z extents) and the cells in
+// the upper shell of one brick (faces x, y, z) that the interpolated adjoint
+// hands to its neighbours.
+#ifndef CTMI_BWD_BX
+#define CTMI_BWD_BX 16
+#endif
+#ifndef CTMI_BWD_BY
+#define CTMI_BWD_BY 16
+#endif
+#ifndef CTMI_BWD_BZ
+#define CTMI_BWD_BZ 8
+#endif
+#define CTMI_HALO_SLOTS \
+    ((CTMI_BWD_BY + 1) * (CTMI_BWD_BZ + 1) + CTMI_BWD_BX * (CTMI_BWD_BZ + 1) + CTMI_BWD_BX * CTMI_BWD_BY)
 
 struct VolDims {
     int nx, ny, nz;
@@ -247,6 +259,24 @@ __device__ __forceinline__ int entry_cell(float S, float d, float a, int step, i
 {
     const float x = __builtin_fmaf(a, d, S);
     int i = step < 0 ? (int)__builtin_ceilf(x) - 1 : (int)__builtin_floorf(x);
+    i = i < lo ? lo : i;
+    i = i > hi - 1 ? hi - 1 : i;
+    return i;
+}
+
+// Cell at parameter a along one axis in the walks' crossing order: the cell
+// entered at a (on a plane, the one the ray moves into), moved back by one
+// when the FP32 crossing parameter of the plane through which the ray enters
+// that cell lies beyond a, then clamped to [lo, hi - 1].  For a ray (nearly)
+// parallel to an axis's planes whose FP32 position rounds onto one of them,
+// the position and the crossing parameters disagree; the walks step by the
+// crossing parameters, so their start cells must follow them too (the
+// forward walk and each adjoint brick then split the ray at the same plane).
+__device__ __forceinline__ int ordered_cell(const SiddonAxis& ax, float S, float d, float a, int lo, int hi)
+{
+    const float x = __builtin_fmaf(a, d, S);
+    int i = ax.step < 0 ? (int)__builtin_ceilf(x) - 1 : (int)__builtin_floorf(x);
+    if (ax.step != 0 && plane_alpha(ax, (float)(i + (ax.step < 0))) > a) i -= ax.step;
     i = i < lo ? lo : i;
     i = i > hi - 1 ? hi - 1 : i;
     return i;

@@ -303,9 +303,9 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
     hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, w.amax);
     hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, w.amax);
     w.alive = active && hit && amin < w.amax;
-    w.ix = entry_cell(S[0], d[0], amin, ax.step, 0, v.nx);
-    w.iy = entry_cell(S[1], d[1], amin, ay.step, 0, v.ny);
-    w.iz = entry_cell(S[2], d[2], amin, az.step, 0, v.nz);
+    w.ix = ordered_cell(ax, S[0], d[0], amin, 0, v.nx);
+    w.iy = ordered_cell(ay, S[1], d[1], amin, 0, v.ny);
+    w.iz = ordered_cell(az, S[2], d[2], amin, 0, v.nz);
     w.qx = (float)(w.ix + (ax.step > 0));
     w.qy = (float)(w.iy + (ay.step > 0));
     w.qz = (float)(w.iz + (az.step > 0));

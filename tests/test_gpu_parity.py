@@ -2,8 +2,8 @@
 
 Tolerances (rel-L2 unless stated): A and A^T 1e-4; FDK 1e-4; CGLS after
 20 iterations 1e-3; GPU dot-product identity 1e-5.  Sizes are chosen so the
-oracle finishes in seconds while spanning several 16x16 ray tiles and 16^3
-bricks with ragged tails.
+oracle finishes in seconds while spanning several 16x16 ray tiles and
+16x16x8 adjoint bricks with ragged tails.
 """
 import numpy as np
 import pytest
@@ -396,3 +396,76 @@ def test_backproject_heavy_tailed_projections(P, orc, kind):
     quiet = np.abs(want - ref) < 1e-12 * np.abs(want).max()
     if quiet.any():
         assert _rel(got[quiet], want[quiet]) < 1e-4
+
+
+def _grazing_geometry(kind):
+    """32 detector rows 2 um apart: every ray lies within 1e-4 rad of the
+    face between the adjoint bricks below and above z = 16, and the source
+    sits 0.0025 voxel below that face (for the interpolated adjoint the face
+    is the plane z = 16 of the samples' lower corners, for Siddon the cell
+    boundary z = 15.5 in voxel-centre coordinates)."""
+    face_off = -4.4975 if kind == "interp" else -3.9975
+    return Geometry(DSD=400.0, DSO=200.0, nVoxel=(24, 16, 64), dVoxel=(1.0, 1.0, 1.0), nDetector=(32, 64),
+                    dDetector=(0.002, 0.25), offOrigin=(face_off, 0.0, 0.0)), np.array([0.0, 0.02, np.pi])
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_adjoint_of_rays_grazing_a_brick_face(P, kind):
+    """Positions within an FP32 rounding of a brick face land on either side
+    of it; each adjoint brick must take exactly the samples (segments) whose
+    FP32 position lies in it, or the GPU's A^T stops being the transpose of
+    its A.  One dropped sample moves the inner products by about 1e-5."""
+    geo, ang = _grazing_geometry(kind)
+    plan = P.Plan(geo, ang)
+    x = _dev(synth.uniform_volume(geo, 42))
+    y = _dev(synth.uniform_projections(geo, len(ang), 43))
+    lhs = float(_host(P.dot(plan.forward(x, kind=kind), y))[0])
+    rhs = float(_host(P.dot(x, plan.backproject(y, kind=kind)))[0])
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs), (kind, lhs, rhs)
+
+
+def test_interp_backproject_rays_grazing_a_brick_face(P, orc):
+    """The same rays against the oracle, voxel by voxel: a sample that
+    neither brick takes would cost a voxel about 1e-3 of its value.  (For
+    Siddon the segment lengths of such rays are ill-conditioned in the
+    source's FP32 position, about 1e-3 of a voxel's value, so only the
+    inner-product check above applies to it.)"""
+    geo, ang = _grazing_geometry("interp")
+    y = synth.uniform_projections(geo, len(ang), 41)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.backproject(_dev(y), kind="interp")).astype(np.float64)
+    want = orc.backward(geo, ang, y.astype(np.float64), "interp")
+    err = np.abs(got - want).max() / np.abs(want).max()
+    assert err < 2e-5, err
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_backproject_rays_in_brick_faces(P, orc, kind):
+    """Odd detector, no offsets, views at multiples of pi/4: the central row
+    and column hold rays with an exactly zero step along an axis, lying
+    exactly in a brick face (z = 8 of the samples' lower corners for 17
+    slices; the cell boundary y = 15.5 for 32 rows at view 0).  Such a ray
+    belongs to exactly one brick.  At pi/2, pi and 3 pi/2 the FP64 sine or
+    cosine leaves a step of ~1e-17 instead of 0, which must not push a
+    sample range out of integer range.  Those three views also put Siddon
+    rays within 1e-13 voxel of a cell plane they run along, closer than FP32
+    positions resolve, so the oracle check of Siddon leaves them out; its A
+    and A^T still have to be each other's transpose there."""
+    geo = Geometry(DSD=500.0, DSO=300.0, nVoxel=(17, 32, 20), dVoxel=(1.0, 1.0, 1.0), nDetector=(31, 33),
+                   dDetector=(1.0, 1.0))
+    ang = synth.circular_angles(8)
+    plan = P.Plan(geo, ang)
+    xd = _dev(synth.uniform_volume(geo, 46))
+    yd = _dev(synth.uniform_projections(geo, len(ang), 47))
+    lhs = float(_host(P.dot(plan.forward(xd, kind=kind), yd))[0])
+    rhs = float(_host(P.dot(xd, plan.backproject(yd, kind=kind)))[0])
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs), (kind, lhs, rhs)
+    if kind == "siddon":
+        ang = ang[[0, 1, 3, 5, 7]]
+        plan = P.Plan(geo, ang)
+    y = synth.uniform_projections(geo, len(ang), 44)
+    got = _host(plan.backproject(_dev(y), kind=kind)).astype(np.float64)
+    want = orc.backward(geo, ang, y.astype(np.float64), kind)
+    assert _rel(got, want) < 1e-5, (kind, _rel(got, want))
+    x = synth.uniform_volume(geo, 45)
+    assert _rel(_host(plan.forward(_dev(x), kind=kind)), orc.forward(geo, ang, x, kind)) < 1e-5
