@@ -478,6 +478,79 @@ __global__ void k_up2(const u16* __restrict__ x, int ldx, int cin, const u16* __
     *reinterpret_cast<uint4*>(out + fv * ldo + cg * 8) = pack8(acc);
 }
 
+// The same transposed convolution on the BF16 MFMA (16x16x32, FP32
+// accumulators), for cin a multiple of 32 and cout of 16 * NT: per
+// sub-position s, D_s[co][v] = sum_ci W[co][s][ci] X[ci][v] is a GEMM with
+// M = cout, N = coarse voxels, K = cin.  A wave owns 16 consecutive coarse
+// voxels (the N columns; lane li reads 8 consecutive channels of voxel
+// v0 + li, a 16-byte load from the channels-last row) and computes all eight
+// sub-positions and all output channels, so every input row is read once;
+// the weights (at most 64 x 8 x 128 BF16) come through L1/L2.  Lane
+// (li, g) ends with channels 16 nt + 4 g .. + 3 of fine voxel 2 v + s.
+template <int NT>
+__global__ __launch_bounds__(256) void k_up2_mfma(const u16* __restrict__ x, int ldx, int cin,
+                                                  const u16* __restrict__ wt, const float* __restrict__ bias, int n,
+                                                  int d, int h, int w, u16* __restrict__ out, int ldo)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+    const int64_t nvox = (int64_t)n * d * h * w;
+    const int64_t v0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (v0 >= nvox) return;   // uniform over the wave
+    const int64_t v = v0 + li;
+    const bool vok = v < nvox;
+    const u16* xr = x + (vok ? v : v0) * ldx + 8 * g;
+    int64_t r = vok ? v : v0;
+    const int cx = (int)(r % w);
+    r /= w;
+    const int cy = (int)(r % h);
+    r /= h;
+    const int cz = (int)(r % d);
+    const int nb = (int)(r / d);
+    const int D = 2 * d, H = 2 * h, W = 2 * w;
+    // sub-positions one at a time (the input row stays in L1 between them)
+    for (int s = 0; s < 8; ++s) {
+        f32x4 acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < cin; kc += 32) {
+            const bf16x8 xb = as_bf16x8(vok ? *reinterpret_cast<const uint4*>(xr + kc) : make_uint4(0, 0, 0, 0));
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const uint4 wf =
+                    *reinterpret_cast<const uint4*>(wt + ((size_t)(nt * 16 + li) * 8 + s) * cin + kc + 8 * g);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(wf), xb, acc[nt], 0, 0, 0);
+            }
+        }
+        // The accumulators are read right after the last MFMA; the compiler
+        // left too few wait states there (the first two of each four read
+        // stale values), so 24 explicit ones are placed between the MFMAs
+        // that define them and the reads, pinned by in/out operands.
+        if constexpr (NT == 1)
+            asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" : "+a"(acc[0]));
+        else if constexpr (NT == 2)
+            asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" : "+a"(acc[0]), "+a"(acc[1]));
+        else
+            asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7"
+                         : "+a"(acc[0]), "+a"(acc[1]), "+a"(acc[2]), "+a"(acc[3]));
+        if (!vok) continue;
+        const int Z = 2 * cz + (s >> 2), Y = 2 * cy + ((s >> 1) & 1), X = 2 * cx + (s & 1);
+        const size_t fv = (((size_t)nb * D + Z) * H + Y) * W + X;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = nt * 16 + 4 * g;
+            float o[4] = {acc[nt][0], acc[nt][1], acc[nt][2], acc[nt][3]};
+            if (bias) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] += bias[co + e];
+            }
+            uint2 q;
+            q.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+            q.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+            *reinterpret_cast<uint2*>(out + fv * ldo + co) = q;
+        }
+    }
+}
+
 // data gradient of up2 with the ReLU mask of its input:
 // dx[v][ci] = bf16(mask(below[v][ci]) sum_s sum_co g[2v + s][co] w[co][s][ci])
 __global__ void k_up2_dgrad(const u16* __restrict__ gr, int ldg, int cout, const u16* __restrict__ wt, int cin,
@@ -778,7 +851,19 @@ hipError_t launch_unet_skip_grad(const uint16_t* e, int lde, const uint16_t* dp,
 hipError_t launch_unet_up2(const uint16_t* x, int ldx, int cin, const uint16_t* wt, const float* bias, int cout,
                            int n, int d, int h, int w, uint16_t* out, int ldo, hipStream_t s)
 {
-    const int64_t total = (int64_t)n * 8 * d * h * w * (cout / 8);
+    const int64_t nvox = (int64_t)n * d * h * w;
+    if (cin % 32 == 0 && (cout == 16 || cout == 32 || cout == 64)) {
+        // one wave per 16 coarse voxels, four waves per workgroup
+        const unsigned blocks = (unsigned)((nvox + 63) / 64);
+        if (cout == 16)
+            k_up2_mfma<1><<<blocks, 256, 0, s>>>(x, ldx, cin, wt, bias, n, d, h, w, out, ldo);
+        else if (cout == 32)
+            k_up2_mfma<2><<<blocks, 256, 0, s>>>(x, ldx, cin, wt, bias, n, d, h, w, out, ldo);
+        else
+            k_up2_mfma<4><<<blocks, 256, 0, s>>>(x, ldx, cin, wt, bias, n, d, h, w, out, ldo);
+        return hipGetLastError();
+    }
+    const int64_t total = nvox * 8 * (cout / 8);
     k_up2<<<blocks_for(total, 256), 256, 0, s>>>(x, ldx, cin, wt, bias, cout, n, d, h, w, out, ldo);
     return hipGetLastError();
 }
