@@ -117,11 +117,22 @@ __device__ __forceinline__ float row_weight(const FilterArgs& fa, int iu, int iv
     return w;
 }
 
+// Radix-4 passes: two consecutive radix-2 stages fused in registers, with
+// the same butterflies, twiddles and rounding as the stages they replace
+// (so the result is that of the radix-2 transform), half the LDS round trips
+// and barriers, and the twiddle table copied to LDS when it fits (TWL).
+// DIF stage pair (span S, then S/2), butterfly t < L/4: Q = S/2, j = t mod Q,
+// elements b + j + {0, Q, 2Q, 3Q} with b = (t / Q) 2S.  DIT stage pair (span
+// S, then 2S): j = t mod S, elements b + j + {0, S, 2S, 3S}, b = (t / S) 4S.
+// An odd stage count leaves one radix-2 stage (the last DIF, the first DIT).
+template <bool TWL>
 __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out, const float* __restrict__ H,
-                                                    const float2* __restrict__ tw, int64_t nrows, FilterArgs fa)
+                                                    const float2* __restrict__ twg, int64_t nrows, FilterArgs fa)
 {
     extern __shared__ float2 buf[];
-    const int L = fa.L;
+    const int L = fa.L, L2 = L >> 1, L4 = L >> 2;
+    float2* const tws = buf + L;
+    const float2* const tw = TWL ? tws : twg;
     const int64_t r0 = 2 * (int64_t)blockIdx.x, r1 = r0 + 1;
     const bool has1 = r1 < nrows;
     const int iv0 = (int)(r0 % fa.nv), iv1 = (int)(r1 % fa.nv);
@@ -135,16 +146,34 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
         }
         buf[n] = make_float2(x, y);
     }
+    if (TWL)
+        for (int n = threadIdx.x; n < L2; n += blockDim.x) tws[n] = twg[n];
     __syncthreads();
-    // forward DIF: spans L/2, L/4, ..., 1; twiddle exp(-2 pi i j / (2 span))
-    for (int span = L >> 1, tstride = 1; span >= 1; span >>= 1, tstride <<= 1) {
-        for (int t = threadIdx.x; t < (L >> 1); t += blockDim.x) {
-            const int j = t & (span - 1);
-            const int i0 = ((t - j) << 1) + j;
-            const int i1 = i0 + span;
-            const float2 u = buf[i0], w = buf[i1];
-            buf[i0] = make_float2(u.x + w.x, u.y + w.y);
-            buf[i1] = cmul(make_float2(u.x - w.x, u.y - w.y), tw[j * tstride]);
+    // forward DIF, stage pairs (S, S/2) from S = L/2; twiddle exp(-2 pi i j / (2 span))
+    int span = L2;
+    for (; span >= 2; span >>= 2) {
+        const int Q = span >> 1, ts = L / (2 * span);
+        for (int t = threadIdx.x; t < L4; t += blockDim.x) {
+            const int j = t & (Q - 1);
+            const int i0 = ((t - j) << 2) + j;   // (t / Q) 2S + j
+            const float2 x0 = buf[i0], x1 = buf[i0 + Q], x2 = buf[i0 + span], x3 = buf[i0 + span + Q];
+            const float2 y0 = make_float2(x0.x + x2.x, x0.y + x2.y);
+            const float2 y2 = cmul(make_float2(x0.x - x2.x, x0.y - x2.y), tw[j * ts]);
+            const float2 y1 = make_float2(x1.x + x3.x, x1.y + x3.y);
+            const float2 y3 = cmul(make_float2(x1.x - x3.x, x1.y - x3.y), tw[(j + Q) * ts]);
+            const float2 c = tw[j * 2 * ts];
+            buf[i0] = make_float2(y0.x + y1.x, y0.y + y1.y);
+            buf[i0 + Q] = cmul(make_float2(y0.x - y1.x, y0.y - y1.y), c);
+            buf[i0 + span] = make_float2(y2.x + y3.x, y2.y + y3.y);
+            buf[i0 + span + Q] = cmul(make_float2(y2.x - y3.x, y2.y - y3.y), c);
+        }
+        __syncthreads();
+    }
+    if (span == 1) {   // odd stage count: the last radix-2 stage (twiddle 1)
+        for (int t = threadIdx.x; t < L2; t += blockDim.x) {
+            const float2 u = buf[2 * t], w = buf[2 * t + 1];
+            buf[2 * t] = make_float2(u.x + w.x, u.y + w.y);
+            buf[2 * t + 1] = cmul(make_float2(u.x - w.x, u.y - w.y), tw[0]);
         }
         __syncthreads();
     }
@@ -155,17 +184,37 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
         buf[n] = make_float2(z.x * h, z.y * h);
     }
     __syncthreads();
-    // inverse DIT: spans 1, 2, ..., L/2; twiddle exp(+2 pi i j / (2 span))
-    for (int span = 1, tstride = L >> 1; span < L; span <<= 1, tstride >>= 1) {
-        for (int t = threadIdx.x; t < (L >> 1); t += blockDim.x) {
+    // inverse DIT; twiddle exp(+2 pi i j / (2 span)).  With an odd stage count
+    // the first stage (span 1, twiddle 1) runs alone.
+    span = 1;
+    if (fa.logL & 1) {
+        for (int t = threadIdx.x; t < L2; t += blockDim.x) {
+            const float2 c = tw[0];
+            const float2 w = cmul(buf[2 * t + 1], make_float2(c.x, -c.y));
+            const float2 u = buf[2 * t];
+            buf[2 * t] = make_float2(u.x + w.x, u.y + w.y);
+            buf[2 * t + 1] = make_float2(u.x - w.x, u.y - w.y);
+        }
+        __syncthreads();
+        span = 2;
+    }
+    for (; span < L; span <<= 2) {
+        const int ts1 = L / (2 * span), ts2 = L / (4 * span);
+        for (int t = threadIdx.x; t < L4; t += blockDim.x) {
             const int j = t & (span - 1);
-            const int i0 = ((t - j) << 1) + j;
-            const int i1 = i0 + span;
-            const float2 c = tw[j * tstride];
-            const float2 w = cmul(buf[i1], make_float2(c.x, -c.y));
-            const float2 u = buf[i0];
-            buf[i0] = make_float2(u.x + w.x, u.y + w.y);
-            buf[i1] = make_float2(u.x - w.x, u.y - w.y);
+            const int i0 = ((t - j) << 2) + j;   // (t / S) 4S + j
+            const float2 c1 = tw[j * ts1], ca = tw[j * ts2], cb = tw[(j + span) * ts2];
+            const float2 x0 = buf[i0], x1 = buf[i0 + span], x2 = buf[i0 + 2 * span], x3 = buf[i0 + 3 * span];
+            const float2 w1 = cmul(x1, make_float2(c1.x, -c1.y));
+            const float2 y0 = make_float2(x0.x + w1.x, x0.y + w1.y), y1 = make_float2(x0.x - w1.x, x0.y - w1.y);
+            const float2 w3 = cmul(x3, make_float2(c1.x, -c1.y));
+            const float2 y2 = make_float2(x2.x + w3.x, x2.y + w3.y), y3 = make_float2(x2.x - w3.x, x2.y - w3.y);
+            const float2 wa = cmul(y2, make_float2(ca.x, -ca.y));
+            const float2 wb = cmul(y3, make_float2(cb.x, -cb.y));
+            buf[i0] = make_float2(y0.x + wa.x, y0.y + wa.y);
+            buf[i0 + 2 * span] = make_float2(y0.x - wa.x, y0.y - wa.y);
+            buf[i0 + span] = make_float2(y1.x + wb.x, y1.y + wb.y);
+            buf[i0 + 3 * span] = make_float2(y1.x - wb.x, y1.y - wb.y);
         }
         __syncthreads();
     }
@@ -213,8 +262,16 @@ hipError_t launch_fdk_filter(const Plan& p, int wang, const float* proj, float* 
     fa.wang_sign = g.offDetector[1] < 0 ? -1.0f : 1.0f;
     const int64_t nrows = nviews * p.det.nv;
     const unsigned blocks = (unsigned)((nrows + 1) / 2);
-    const size_t lds = sizeof(float2) * (size_t)p.fft_len;
-    hipLaunchKernelGGL(k_fdk_filter, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle, nrows, fa);
+    // the row and, up to L = 4096 (48 KB), the twiddle table in LDS
+    if (p.fft_len <= 4096) {
+        const size_t lds = sizeof(float2) * (size_t)(p.fft_len + p.fft_len / 2);
+        hipLaunchKernelGGL(k_fdk_filter<true>, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle,
+                           nrows, fa);
+    } else {
+        const size_t lds = sizeof(float2) * (size_t)p.fft_len;
+        hipLaunchKernelGGL(k_fdk_filter<false>, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle,
+                           nrows, fa);
+    }
     return hipGetLastError();
 }
 
