@@ -117,21 +117,140 @@ __device__ __forceinline__ float row_weight(const FilterArgs& fa, int iu, int iv
     return w;
 }
 
-// Radix-4 passes: two consecutive radix-2 stages fused in registers, with
-// the same butterflies, twiddles and rounding as the stages they replace
-// (so the result is that of the radix-2 transform), half the LDS round trips
-// and barriers, and the twiddle table copied to LDS when it fits (TWL).
-// DIF stage pair (span S, then S/2), butterfly t < L/4: Q = S/2, j = t mod Q,
-// elements b + j + {0, Q, 2Q, 3Q} with b = (t / Q) 2S.  DIT stage pair (span
-// S, then 2S): j = t mod S, elements b + j + {0, S, 2S, 3S}, b = (t / S) 4S.
-// An odd stage count leaves one radix-2 stage (the last DIF, the first DIT).
-template <bool TWL>
+// LDS slot of row element i: one float2 of padding per 16 (P) breaks the
+// power-of-two strides of the small-span passes across the LDS banks.
+template <bool P>
+__device__ __forceinline__ int pad(int i) { return P ? i + (i >> 4) : i; }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
+
+// Consecutive radix-2 stages are fused into radix-8 (three stages) and
+// radix-4 (two) passes in registers, with the same butterflies, twiddles and
+// rounding as the stages they replace, so the result is that of the
+// radix-2 transform with a third of its LDS round trips and barriers.
+// tw[k] = exp(-2 pi i k / L), k < L/2; a radix-2 stage of span S uses
+// tw[j L / (2 S)] for the pair at offset j of its block.
+//
+// DIF pass over stages S, S/2, S/4 (E = S/4): butterfly t < L/8 takes
+// elements i0 + k E, k < 8, i0 = (t / E) 2S + t mod E.
+template <bool P>
+__device__ __forceinline__ void dif8(float2* buf, const float2* tw, int L, int S)
+{
+    const int E = S >> 2, ts1 = L / (2 * S);
+    for (int t = threadIdx.x; t < (L >> 3); t += blockDim.x) {
+        const int j = t & (E - 1);
+        const int i0 = ((t - j) << 3) + j;
+        float2 x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = buf[pad<P>(i0 + k * E)];
+        float2 y[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            y[k] = cadd(x[k], x[k + 4]);
+            y[k + 4] = cmul(csub(x[k], x[k + 4]), tw[(j + k * E) * ts1]);
+        }
+        const float2 c0 = tw[j * 2 * ts1], c1 = tw[(j + E) * 2 * ts1], c3 = tw[j * 4 * ts1];
+#pragma unroll
+        for (int q = 0; q < 8; q += 4) {
+            const float2 z0 = cadd(y[q], y[q + 2]), z2 = cmul(csub(y[q], y[q + 2]), c0);
+            const float2 z1 = cadd(y[q + 1], y[q + 3]), z3 = cmul(csub(y[q + 1], y[q + 3]), c1);
+            buf[pad<P>(i0 + q * E)] = cadd(z0, z1);
+            buf[pad<P>(i0 + (q + 1) * E)] = cmul(csub(z0, z1), c3);
+            buf[pad<P>(i0 + (q + 2) * E)] = cadd(z2, z3);
+            buf[pad<P>(i0 + (q + 3) * E)] = cmul(csub(z2, z3), c3);
+        }
+    }
+}
+
+// DIF pass over stages S, S/2 (Q = S/2): elements i0 + {0, Q, 2Q, 3Q},
+// i0 = (t / Q) 2S + t mod Q.
+template <bool P>
+__device__ __forceinline__ void dif4(float2* buf, const float2* tw, int L, int S)
+{
+    const int Q = S >> 1, ts = L / (2 * S);
+    for (int t = threadIdx.x; t < (L >> 2); t += blockDim.x) {
+        const int j = t & (Q - 1);
+        const int i0 = ((t - j) << 2) + j;
+        const float2 x0 = buf[pad<P>(i0)], x1 = buf[pad<P>(i0 + Q)], x2 = buf[pad<P>(i0 + S)], x3 = buf[pad<P>(i0 + S + Q)];
+        const float2 y0 = cadd(x0, x2), y2 = cmul(csub(x0, x2), tw[j * ts]);
+        const float2 y1 = cadd(x1, x3), y3 = cmul(csub(x1, x3), tw[(j + Q) * ts]);
+        const float2 c = tw[j * 2 * ts];
+        buf[pad<P>(i0)] = cadd(y0, y1);
+        buf[pad<P>(i0 + Q)] = cmul(csub(y0, y1), c);
+        buf[pad<P>(i0 + S)] = cadd(y2, y3);
+        buf[pad<P>(i0 + S + Q)] = cmul(csub(y2, y3), c);
+    }
+}
+
+// DIT pass over stages S, 2S, 4S: elements i0 + k S, k < 8,
+// i0 = (t / S) 8S + t mod S.
+template <bool P>
+__device__ __forceinline__ void dit8(float2* buf, const float2* tw, int L, int S)
+{
+    const int ts1 = L / (2 * S);
+    for (int t = threadIdx.x; t < (L >> 3); t += blockDim.x) {
+        const int j = t & (S - 1);
+        const int i0 = ((t - j) << 3) + j;
+        float2 x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = buf[pad<P>(i0 + k * S)];
+        const float2 c1 = conj2(tw[j * ts1]);
+        float2 y[8];
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            const float2 w = cmul(x[k + 1], c1);
+            y[k] = cadd(x[k], w);
+            y[k + 1] = csub(x[k], w);
+        }
+        const float2 ca = conj2(tw[j * (ts1 >> 1)]), cb = conj2(tw[(j + S) * (ts1 >> 1)]);
+        float2 z[8];
+#pragma unroll
+        for (int q = 0; q < 8; q += 4) {
+            const float2 wa = cmul(y[q + 2], ca), wb = cmul(y[q + 3], cb);
+            z[q] = cadd(y[q], wa);
+            z[q + 2] = csub(y[q], wa);
+            z[q + 1] = cadd(y[q + 1], wb);
+            z[q + 3] = csub(y[q + 1], wb);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float2 w = cmul(z[k + 4], conj2(tw[(j + k * S) * (ts1 >> 2)]));
+            buf[pad<P>(i0 + k * S)] = cadd(z[k], w);
+            buf[pad<P>(i0 + (k + 4) * S)] = csub(z[k], w);
+        }
+    }
+}
+
+// DIT pass over stages S, 2S: elements i0 + {0, S, 2S, 3S}, i0 = (t / S) 4S + t mod S.
+template <bool P>
+__device__ __forceinline__ void dit4(float2* buf, const float2* tw, int L, int S)
+{
+    const int ts1 = L / (2 * S), ts2 = ts1 >> 1;
+    for (int t = threadIdx.x; t < (L >> 2); t += blockDim.x) {
+        const int j = t & (S - 1);
+        const int i0 = ((t - j) << 2) + j;
+        const float2 c1 = conj2(tw[j * ts1]), ca = conj2(tw[j * ts2]), cb = conj2(tw[(j + S) * ts2]);
+        const float2 x0 = buf[pad<P>(i0)], x1 = buf[pad<P>(i0 + S)], x2 = buf[pad<P>(i0 + 2 * S)], x3 = buf[pad<P>(i0 + 3 * S)];
+        const float2 w1 = cmul(x1, c1), w3 = cmul(x3, c1);
+        const float2 y0 = cadd(x0, w1), y1 = csub(x0, w1), y2 = cadd(x2, w3), y3 = csub(x2, w3);
+        const float2 wa = cmul(y2, ca), wb = cmul(y3, cb);
+        buf[pad<P>(i0)] = cadd(y0, wa);
+        buf[pad<P>(i0 + 2 * S)] = csub(y0, wa);
+        buf[pad<P>(i0 + S)] = cadd(y1, wb);
+        buf[pad<P>(i0 + 3 * S)] = csub(y1, wb);
+    }
+}
+
+// The twiddle table is copied to LDS when it fits (TWL).
+template <bool TWL, bool P = TWL>
 __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out, const float* __restrict__ H,
                                                     const float2* __restrict__ twg, int64_t nrows, FilterArgs fa)
 {
     extern __shared__ float2 buf[];
-    const int L = fa.L, L2 = L >> 1, L4 = L >> 2;
-    float2* const tws = buf + L;
+    const int L = fa.L, L2 = L >> 1;
+    float2* const tws = buf + L + (P ? L >> 4 : 0);
     const float2* const tw = TWL ? tws : twg;
     const int64_t r0 = 2 * (int64_t)blockIdx.x, r1 = r0 + 1;
     const bool has1 = r1 < nrows;
@@ -144,85 +263,62 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
             x = a[n] * row_weight(fa, n, iv0);
             if (has1) y = bb[n] * row_weight(fa, n, iv1);
         }
-        buf[n] = make_float2(x, y);
+        buf[pad<P>(n)] = make_float2(x, y);
     }
     if (TWL)
         for (int n = threadIdx.x; n < L2; n += blockDim.x) tws[n] = twg[n];
     __syncthreads();
-    // forward DIF, stage pairs (S, S/2) from S = L/2; twiddle exp(-2 pi i j / (2 span))
-    int span = L2;
-    for (; span >= 2; span >>= 2) {
-        const int Q = span >> 1, ts = L / (2 * span);
-        for (int t = threadIdx.x; t < L4; t += blockDim.x) {
-            const int j = t & (Q - 1);
-            const int i0 = ((t - j) << 2) + j;   // (t / Q) 2S + j
-            const float2 x0 = buf[i0], x1 = buf[i0 + Q], x2 = buf[i0 + span], x3 = buf[i0 + span + Q];
-            const float2 y0 = make_float2(x0.x + x2.x, x0.y + x2.y);
-            const float2 y2 = cmul(make_float2(x0.x - x2.x, x0.y - x2.y), tw[j * ts]);
-            const float2 y1 = make_float2(x1.x + x3.x, x1.y + x3.y);
-            const float2 y3 = cmul(make_float2(x1.x - x3.x, x1.y - x3.y), tw[(j + Q) * ts]);
-            const float2 c = tw[j * 2 * ts];
-            buf[i0] = make_float2(y0.x + y1.x, y0.y + y1.y);
-            buf[i0 + Q] = cmul(make_float2(y0.x - y1.x, y0.y - y1.y), c);
-            buf[i0 + span] = make_float2(y2.x + y3.x, y2.y + y3.y);
-            buf[i0 + span + Q] = cmul(make_float2(y2.x - y3.x, y2.y - y3.y), c);
-        }
+    // forward DIF from span L/2: radix-8 passes, then the one or two stages left
+    int span = L2, rem = fa.logL;
+    for (; rem >= 3; rem -= 3, span >>= 3) {
+        dif8<P>(buf, tw, L, span);
         __syncthreads();
     }
-    if (span == 1) {   // odd stage count: the last radix-2 stage (twiddle 1)
+    if (rem == 2) {
+        dif4<P>(buf, tw, L, span);
+        __syncthreads();
+    } else if (rem == 1) {   // span 1, twiddle tw[0]
         for (int t = threadIdx.x; t < L2; t += blockDim.x) {
-            const float2 u = buf[2 * t], w = buf[2 * t + 1];
-            buf[2 * t] = make_float2(u.x + w.x, u.y + w.y);
-            buf[2 * t + 1] = cmul(make_float2(u.x - w.x, u.y - w.y), tw[0]);
+            const float2 u = buf[pad<P>(2 * t)], w = buf[pad<P>(2 * t + 1)];
+            buf[pad<P>(2 * t)] = cadd(u, w);
+            buf[pad<P>(2 * t + 1)] = cmul(csub(u, w), tw[0]);
         }
         __syncthreads();
     }
     // response (bit-reversed order, 1/L and tau folded in) times the angular scale
     for (int n = threadIdx.x; n < L; n += blockDim.x) {
         const float h = H[n] * fa.scale;
-        const float2 z = buf[n];
-        buf[n] = make_float2(z.x * h, z.y * h);
+        const float2 z = buf[pad<P>(n)];
+        buf[pad<P>(n)] = make_float2(z.x * h, z.y * h);
     }
     __syncthreads();
-    // inverse DIT; twiddle exp(+2 pi i j / (2 span)).  With an odd stage count
-    // the first stage (span 1, twiddle 1) runs alone.
+    // inverse DIT from span 1: the one or two stages left over first, then
+    // radix-8 passes
     span = 1;
-    if (fa.logL & 1) {
+    rem = fa.logL % 3;
+    if (rem == 1) {
         for (int t = threadIdx.x; t < L2; t += blockDim.x) {
-            const float2 c = tw[0];
-            const float2 w = cmul(buf[2 * t + 1], make_float2(c.x, -c.y));
-            const float2 u = buf[2 * t];
-            buf[2 * t] = make_float2(u.x + w.x, u.y + w.y);
-            buf[2 * t + 1] = make_float2(u.x - w.x, u.y - w.y);
+            const float2 w = cmul(buf[pad<P>(2 * t + 1)], conj2(tw[0]));
+            const float2 u = buf[pad<P>(2 * t)];
+            buf[pad<P>(2 * t)] = cadd(u, w);
+            buf[pad<P>(2 * t + 1)] = csub(u, w);
         }
         __syncthreads();
         span = 2;
+    } else if (rem == 2) {
+        dit4<P>(buf, tw, L, 1);
+        __syncthreads();
+        span = 4;
     }
-    for (; span < L; span <<= 2) {
-        const int ts1 = L / (2 * span), ts2 = L / (4 * span);
-        for (int t = threadIdx.x; t < L4; t += blockDim.x) {
-            const int j = t & (span - 1);
-            const int i0 = ((t - j) << 2) + j;   // (t / S) 4S + j
-            const float2 c1 = tw[j * ts1], ca = tw[j * ts2], cb = tw[(j + span) * ts2];
-            const float2 x0 = buf[i0], x1 = buf[i0 + span], x2 = buf[i0 + 2 * span], x3 = buf[i0 + 3 * span];
-            const float2 w1 = cmul(x1, make_float2(c1.x, -c1.y));
-            const float2 y0 = make_float2(x0.x + w1.x, x0.y + w1.y), y1 = make_float2(x0.x - w1.x, x0.y - w1.y);
-            const float2 w3 = cmul(x3, make_float2(c1.x, -c1.y));
-            const float2 y2 = make_float2(x2.x + w3.x, x2.y + w3.y), y3 = make_float2(x2.x - w3.x, x2.y - w3.y);
-            const float2 wa = cmul(y2, make_float2(ca.x, -ca.y));
-            const float2 wb = cmul(y3, make_float2(cb.x, -cb.y));
-            buf[i0] = make_float2(y0.x + wa.x, y0.y + wa.y);
-            buf[i0 + 2 * span] = make_float2(y0.x - wa.x, y0.y - wa.y);
-            buf[i0 + span] = make_float2(y1.x + wb.x, y1.y + wb.y);
-            buf[i0 + 3 * span] = make_float2(y1.x - wb.x, y1.y - wb.y);
-        }
+    for (; span < L; span <<= 3) {
+        dit8<P>(buf, tw, L, span);
         __syncthreads();
     }
     float* oa = out + r0 * fa.nu;
     float* ob = out + r1 * fa.nu;
     for (int n = threadIdx.x; n < fa.nu; n += blockDim.x) {
-        oa[n] = buf[n].x;
-        if (has1) ob[n] = buf[n].y;
+        oa[n] = buf[pad<P>(n)].x;
+        if (has1) ob[n] = buf[pad<P>(n)].y;
     }
 }
 
@@ -262,12 +358,13 @@ hipError_t launch_fdk_filter(const Plan& p, int wang, const float* proj, float* 
     fa.wang_sign = g.offDetector[1] < 0 ? -1.0f : 1.0f;
     const int64_t nrows = nviews * p.det.nv;
     const unsigned blocks = (unsigned)((nrows + 1) / 2);
-    // the row and, up to L = 4096 (48 KB), the twiddle table in LDS
+    // up to L = 4096 the padded row and the twiddle table in LDS (51 KB)
+    const size_t row = (size_t)p.fft_len + (size_t)(p.fft_len >> 4);   // padded row
     if (p.fft_len <= 4096) {
-        const size_t lds = sizeof(float2) * (size_t)(p.fft_len + p.fft_len / 2);
+        const size_t lds = sizeof(float2) * (row + (size_t)p.fft_len / 2);
         hipLaunchKernelGGL(k_fdk_filter<true>, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle,
                            nrows, fa);
-    } else {
+    } else {   // L = 8192: the unpadded row alone fills 64 KB
         const size_t lds = sizeof(float2) * (size_t)p.fft_len;
         hipLaunchKernelGGL(k_fdk_filter<false>, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle,
                            nrows, fa);
