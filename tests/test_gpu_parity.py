@@ -138,6 +138,22 @@ def test_fdk_filter_wang_and_odd_rows(P, orc):
     assert _rel(_host(t), want) < 1e-5
 
 
+@pytest.mark.parametrize("nu", [1, 2, 3, 5, 9, 17, 100, 200, 300, 700, 1500, 2100])
+def test_fdk_filter_every_fft_length(P, orc, nu):
+    """Detector widths whose padded FFT lengths run from 2 to 8192: every
+    mix of radix-8, radix-4 and radix-2 passes, the padded LDS row with LDS
+    twiddles up to 4096 and the unpadded row with global twiddles at 8192;
+    three rows leave one unpaired."""
+    geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(3, nu),
+                   dDetector=(0.5, 0.5))
+    ang = synth.circular_angles(2)
+    y = synth.uniform_projections(geo, len(ang), 30 + nu)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.fdk_filter(_dev(y)))
+    want = orc.fdk_filter(geo, y, len(ang))
+    assert _rel(got, want) < 1e-5, (nu, _rel(got, want))
+
+
 def test_bfdk_matches_oracle(P, orc):
     geo, ang = RAGGED, _angles(24, 12)
     y = synth.uniform_projections(geo, len(ang), 13)
