@@ -13,10 +13,37 @@ namespace {
 // call is accumulated in registers, so each output voxel is written once.
 // On a circular orbit W and fu do not depend on z, so per view a thread
 // computes one reciprocal and then walks its ZC voxels along v.
-constexpr int FDK_TX = 32, FDK_TY = 8, FDK_ZC = 8;
+//
+// Views are taken FDK_VB at a time: the detector footprint of the
+// workgroup's voxel block in each view (bounding box of its 8 projected
+// corners, one pixel of margin below and two above, clamped to the
+// detector) is staged in LDS with coalesced row reads, and the bilinear
+// taps read LDS.  A footprint larger than FDK_CAP pixels (or a block corner
+// not in front of the source) reads its view from global memory instead.
+// The values read are the same either way, so the result does not depend on
+// the path.
+#ifndef CTMI_FDK_TX
+#define CTMI_FDK_TX 32
+#endif
+#ifndef CTMI_FDK_ZC
+#define CTMI_FDK_ZC 16
+#endif
+constexpr int FDK_TX = CTMI_FDK_TX, FDK_TY = 256 / FDK_TX, FDK_ZC = CTMI_FDK_ZC;
+#ifndef CTMI_FDK_VB
+#define CTMI_FDK_VB 2
+#endif
+#ifndef CTMI_FDK_CAP
+#define CTMI_FDK_CAP 2560
+#endif
+constexpr int FDK_VB = CTMI_FDK_VB, FDK_CAP = CTMI_FDK_CAP;
 #ifndef CTMI_FDK_XCD
 #define CTMI_FDK_XCD 0
 #endif
+
+struct FdkBox {
+    int u0, v0, w, h;   // staged pixels [u0, u0 + w) x [v0, v0 + h); w = 0: not staged
+    float rw;           // 1 / w
+};
 
 __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __restrict__ proj,
                                                                  float* __restrict__ vol,
@@ -24,49 +51,135 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
                                                                  int nviews, VolDims v, DetDims det, int nbx,
                                                                  int nby, float beta)
 {
+    __shared__ float box[FDK_VB][FDK_CAP];
+    __shared__ FdkBox fb[FDK_VB];
     const int b = CTMI_FDK_XCD ? (int)xcd_contiguous(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int ix = bx * FDK_TX + (int)(threadIdx.x % FDK_TX);
     const int iy = by * FDK_TY + (int)(threadIdx.x / FDK_TX);
     const int iz0 = bz * FDK_ZC;
-    if (ix >= v.nx || iy >= v.ny) return;
+    const bool live = ix < v.nx && iy < v.ny;   // every thread takes part in staging
+    // the block's voxel centres (clamped to the volume)
+    const float lo[3] = {(float)(bx * FDK_TX), (float)(by * FDK_TY), (float)iz0};
+    const float hi[3] = {(float)(min((bx + 1) * FDK_TX, v.nx) - 1), (float)(min((by + 1) * FDK_TY, v.ny) - 1),
+                         (float)(min(iz0 + FDK_ZC, v.nz) - 1)};
     const float fx = (float)ix, fy = (float)iy, fz0 = (float)iz0;
     float acc[FDK_ZC];
 #pragma unroll
     for (int z = 0; z < FDK_ZC; ++z) acc[z] = 0.0f;
 
-    for (int k = 0; k < nviews; ++k) {
-        const ViewGeo& g = tab[view0 + k];
-        const float W = __builtin_fmaf(g.MW[0], fx, __builtin_fmaf(g.MW[1], fy, g.MW[3]));
-        const float rw = 1.0f / W;
-        const float fu = __builtin_fmaf(g.MU[0], fx, __builtin_fmaf(g.MU[1], fy, g.MU[3])) * rw;
-        const float fv0 = __builtin_fmaf(g.MV[2], fz0, __builtin_fmaf(g.MV[0], fx, __builtin_fmaf(g.MV[1], fy, g.MV[3]))) * rw;
-        const float dfv = g.MV[2] * rw;
-        const float wt = rw * rw;
-        const float flu = __builtin_floorf(fu);
-        const int iu = (int)flu;
-        const float au = fu - flu;
-        const float wu0 = (unsigned)iu < (unsigned)det.nu ? 1.0f - au : 0.0f;
-        const float wu1 = (unsigned)(iu + 1) < (unsigned)det.nu ? au : 0.0f;
-        if (wu0 == 0.0f && wu1 == 0.0f) continue;
-        const int u0 = min(max(iu, 0), det.nu - 1), u1 = min(max(iu + 1, 0), det.nu - 1);
-        const float* pk = proj + (int64_t)k * det.nv * det.nu;
+    for (int k0 = 0; k0 < nviews; k0 += FDK_VB) {
+        const int nb = min(FDK_VB, nviews - k0);
+        __syncthreads();   // the previous chunk's reads of box and fb are done
+        if ((int)threadIdx.x < nb) {
+            const ViewGeo& g = tab[view0 + k0 + threadIdx.x];
+            float umin = CTMI_INF, umax = -CTMI_INF, vmin = CTMI_INF, vmax = -CTMI_INF, wmin = CTMI_INF;
 #pragma unroll
-        for (int z = 0; z < FDK_ZC; ++z) {
-            const float fv = __builtin_fmaf((float)z, dfv, fv0);
-            const float flv = __builtin_floorf(fv);
-            const int iv = (int)flv;
-            const float av = fv - flv;
-            const float wv0 = (unsigned)iv < (unsigned)det.nv ? 1.0f - av : 0.0f;
-            const float wv1 = (unsigned)(iv + 1) < (unsigned)det.nv ? av : 0.0f;
-            const int v0 = min(max(iv, 0), det.nv - 1), v1 = min(max(iv + 1, 0), det.nv - 1);
-            const float* r0 = pk + (int64_t)v0 * det.nu;
-            const float* r1 = pk + (int64_t)v1 * det.nu;
-            const float s0 = __builtin_fmaf(wu0, r0[u0], wu1 * r0[u1]);
-            const float s1 = __builtin_fmaf(wu0, r1[u0], wu1 * r1[u1]);
-            acc[z] = __builtin_fmaf(wt, __builtin_fmaf(wv0, s0, wv1 * s1), acc[z]);
+            for (int q = 0; q < 8; ++q) {
+                const float cx = (q & 1) ? hi[0] : lo[0], cy = (q & 2) ? hi[1] : lo[1], cz = (q & 4) ? hi[2] : lo[2];
+                const float W = __builtin_fmaf(g.MW[0], cx, __builtin_fmaf(g.MW[1], cy, __builtin_fmaf(g.MW[2], cz, g.MW[3])));
+                const float U = __builtin_fmaf(g.MU[0], cx, __builtin_fmaf(g.MU[1], cy, __builtin_fmaf(g.MU[2], cz, g.MU[3])));
+                const float V = __builtin_fmaf(g.MV[0], cx, __builtin_fmaf(g.MV[1], cy, __builtin_fmaf(g.MV[2], cz, g.MV[3])));
+                const float rw = 1.0f / W;
+                wmin = fminf(wmin, W);
+                umin = fminf(umin, U * rw);
+                umax = fmaxf(umax, U * rw);
+                vmin = fminf(vmin, V * rw);
+                vmax = fmaxf(vmax, V * rw);
+            }
+            FdkBox f;
+            f.w = 0;
+            f.u0 = f.v0 = f.h = 0;
+            f.rw = 1.0f;
+            // clamp in float first: corners may project far off the detector
+            umin = fminf(fmaxf(umin, -4.0f), (float)det.nu + 4.0f);
+            umax = fminf(fmaxf(umax, -4.0f), (float)det.nu + 4.0f);
+            vmin = fminf(fmaxf(vmin, -4.0f), (float)det.nv + 4.0f);
+            vmax = fminf(fmaxf(vmax, -4.0f), (float)det.nv + 4.0f);
+            const int u0 = max((int)__builtin_floorf(umin) - 1, 0), u1 = min((int)__builtin_floorf(umax) + 2, det.nu - 1);
+            const int v0 = max((int)__builtin_floorf(vmin) - 1, 0), v1 = min((int)__builtin_floorf(vmax) + 2, det.nv - 1);
+            if (wmin > 0.0f && u0 <= u1 && v0 <= v1 && (u1 - u0 + 1) * (v1 - v0 + 1) <= FDK_CAP) {
+                f.u0 = u0;
+                f.v0 = v0;
+                f.w = u1 - u0 + 1;
+                f.h = v1 - v0 + 1;
+                f.rw = 1.0f / (float)f.w;
+            }
+            fb[threadIdx.x] = f;
+        }
+        __syncthreads();
+        for (int q = 0; q < nb; ++q) {
+            const FdkBox f = fb[q];
+            if (f.w == 0) continue;
+            const float* pk = proj + (int64_t)(k0 + q) * det.nv * det.nu;
+            const int n = f.w * f.h;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                // row i / w from FP32 ((i + 1/2) / w is at least 1/(2w) from an integer)
+                const int r = (int)(((float)i + 0.5f) * f.rw);
+                box[q][i] = pk[(int64_t)(f.v0 + r) * det.nu + f.u0 + (i - r * f.w)];
+            }
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int q = 0; q < nb; ++q) {
+            const int k = k0 + q;
+            const ViewGeo& g = tab[view0 + k];
+            const float W = __builtin_fmaf(g.MW[0], fx, __builtin_fmaf(g.MW[1], fy, g.MW[3]));
+            const float rw = 1.0f / W;
+            const float fu = __builtin_fmaf(g.MU[0], fx, __builtin_fmaf(g.MU[1], fy, g.MU[3])) * rw;
+            const float fv0 = __builtin_fmaf(g.MV[2], fz0, __builtin_fmaf(g.MV[0], fx, __builtin_fmaf(g.MV[1], fy, g.MV[3]))) * rw;
+            const float dfv = g.MV[2] * rw;
+            const float wt = rw * rw;
+            const float flu = __builtin_floorf(fu);
+            const int iu = (int)flu;
+            const float au = fu - flu;
+            const float wu0 = (unsigned)iu < (unsigned)det.nu ? 1.0f - au : 0.0f;
+            const float wu1 = (unsigned)(iu + 1) < (unsigned)det.nu ? au : 0.0f;
+            if (wu0 == 0.0f && wu1 == 0.0f) continue;
+            const int u0 = min(max(iu, 0), det.nu - 1), u1 = min(max(iu + 1, 0), det.nu - 1);
+            const FdkBox f = fb[q];
+            if (f.w > 0) {
+                // staged: LDS offsets clamped into the box (a no-op when the
+                // footprint holds the taps, which its margins ensure)
+                const int c0 = min(max(u0 - f.u0, 0), f.w - 1), c1 = min(max(u1 - f.u0, 0), f.w - 1);
+                const float* bq = box[q];
+#pragma unroll
+                for (int z = 0; z < FDK_ZC; ++z) {
+                    const float fv = __builtin_fmaf((float)z, dfv, fv0);
+                    const float flv = __builtin_floorf(fv);
+                    const int iv = (int)flv;
+                    const float av = fv - flv;
+                    const float wv0 = (unsigned)iv < (unsigned)det.nv ? 1.0f - av : 0.0f;
+                    const float wv1 = (unsigned)(iv + 1) < (unsigned)det.nv ? av : 0.0f;
+                    const int r0 = min(max(min(max(iv, 0), det.nv - 1) - f.v0, 0), f.h - 1);
+                    const int r1 = min(max(min(max(iv + 1, 0), det.nv - 1) - f.v0, 0), f.h - 1);
+                    const float* p0 = bq + r0 * f.w;
+                    const float* p1 = bq + r1 * f.w;
+                    const float s0 = __builtin_fmaf(wu0, p0[c0], wu1 * p0[c1]);
+                    const float s1 = __builtin_fmaf(wu0, p1[c0], wu1 * p1[c1]);
+                    acc[z] = __builtin_fmaf(wt, __builtin_fmaf(wv0, s0, wv1 * s1), acc[z]);
+                }
+            } else {
+                const float* pk = proj + (int64_t)k * det.nv * det.nu;
+#pragma unroll
+                for (int z = 0; z < FDK_ZC; ++z) {
+                    const float fv = __builtin_fmaf((float)z, dfv, fv0);
+                    const float flv = __builtin_floorf(fv);
+                    const int iv = (int)flv;
+                    const float av = fv - flv;
+                    const float wv0 = (unsigned)iv < (unsigned)det.nv ? 1.0f - av : 0.0f;
+                    const float wv1 = (unsigned)(iv + 1) < (unsigned)det.nv ? av : 0.0f;
+                    const int v0 = min(max(iv, 0), det.nv - 1), v1 = min(max(iv + 1, 0), det.nv - 1);
+                    const float* r0 = pk + (int64_t)v0 * det.nu;
+                    const float* r1 = pk + (int64_t)v1 * det.nu;
+                    const float s0 = __builtin_fmaf(wu0, r0[u0], wu1 * r0[u1]);
+                    const float s1 = __builtin_fmaf(wu0, r1[u0], wu1 * r1[u1]);
+                    acc[z] = __builtin_fmaf(wt, __builtin_fmaf(wv0, s0, wv1 * s1), acc[z]);
+                }
+            }
         }
     }
+    if (!live) return;
 #pragma unroll
     for (int z = 0; z < FDK_ZC; ++z) {
         const int iz = iz0 + z;
