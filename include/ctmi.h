@@ -100,7 +100,8 @@ const char* ctmi_version(void);
 /* Validate a geometry without touching the GPU.  Checks: positive sizes and
  * spacings, DSD > DSO, the volume's circumscribed sphere (grown by one voxel)
  * strictly between the source and the detector plane, finite angles,
- * nvox < 2^31.  Returns CTMI_OK, CTMI_EINVAL, CTMI_EUNSUPPORTED or
+ * nvox < 2^31, nu <= 4096 and nu * nv < 2^28 detector pixels.  Returns
+ * CTMI_OK, CTMI_EINVAL, CTMI_EUNSUPPORTED or
  * CTMI_EOVERFLOW.  `angles` is a HOST array of nviews z1 angles (rad). */
 int ctmi_geometry_check(const ctmi_geometry* geo, const double* angles, int64_t nviews);
 

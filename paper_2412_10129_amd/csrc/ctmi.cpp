@@ -59,6 +59,8 @@ int check_sizes(const ctmi_geometry* g, int64_t nviews)
     if ((double)nx * ny * nz >= 2147483648.0) return fail(CTMI_EOVERFLOW, "volume must hold < 2^31 voxels");
     const int64_t nv = g->nDetector[0], nu = g->nDetector[1];
     if (nu > 4096 || nv > (1 << 20)) return fail(CTMI_EOVERFLOW, "detector must have nu <= 4096");
+    // the adjoints count a group of 8 views' footprint pixels in int32
+    if (nu * nv >= (int64_t)1 << 28) return fail(CTMI_EOVERFLOW, "detector must hold < 2^28 pixels");
     if (nviews > (1 << 24)) return fail(CTMI_EOVERFLOW, "too many views");
     // the interpolated projector's samples of one ray inside the volume (its
     // diagonal over the step) must stay below 2^15

@@ -98,7 +98,9 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
             vmax = fminf(fmaxf(vmax, -4.0f), (float)det.nv + 4.0f);
             const int u0 = max((int)__builtin_floorf(umin) - 1, 0), u1 = min((int)__builtin_floorf(umax) + 2, det.nu - 1);
             const int v0 = max((int)__builtin_floorf(vmin) - 1, 0), v1 = min((int)__builtin_floorf(vmax) + 2, det.nv - 1);
-            if (wmin > 0.0f && u0 <= u1 && v0 <= v1 && (u1 - u0 + 1) * (v1 - v0 + 1) <= FDK_CAP) {
+            // (each side is checked first, so the product cannot overflow)
+            if (wmin > 0.0f && u0 <= u1 && v0 <= v1 && u1 - u0 < FDK_CAP && v1 - v0 < FDK_CAP &&
+                (u1 - u0 + 1) * (v1 - v0 + 1) <= FDK_CAP) {
                 f.u0 = u0;
                 f.v0 = v0;
                 f.w = u1 - u0 + 1;
