@@ -107,6 +107,12 @@ def test_bad_angles_and_sizes(ctmi):
     from paper_2412_10129_amd import CtmiError
     with pytest.raises(CtmiError):
         ctmi.geometry_check(big, ang)
+    # detectors: nu <= 4096, and fewer than 2^28 pixels (int32 footprint counts)
+    with pytest.raises(CtmiError, match="nu <= 4096"):
+        ctmi.geometry_check(geo.replace(nDetector=(64, 4097)), ang)
+    with pytest.raises(CtmiError, match="2\\^28"):
+        ctmi.geometry_check(geo.replace(nDetector=(65536, 4096), dDetector=(0.001, 0.001)), ang)
+    ctmi.geometry_check(geo.replace(nDetector=(65535, 4096), dDetector=(0.001, 0.001)), ang)
 
 
 def test_null_arguments_fail_before_any_device_call(ctmi):
