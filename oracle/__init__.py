@@ -492,7 +492,7 @@ def awtv_grad(x, delta: float = math.inf, eps: float = 1e-8):
 def asd_pocs(geo: Geometry, angles, b, niter: int, blocksize: int = 1, kind: str = "interp", lam: float = 1.0,
              lam_red: float = 0.99, alpha: float = 0.002, alpha_red: float = 0.95, ng: int = 20,
              rmax: float = 0.95, eps_data: float = 0.0, delta: float = math.inf, eps_tv: float = 1e-8,
-             nonneg: bool = True, x0=None):
+             nonneg: bool = True, x0=None, trace=None):
     """ASD-POCS and OS-ASD-POCS (the POCS class of section 2.2: a data
     step alternated with adaptive TV steepest descent, after Sidky and Pan;
     OS version with blocks of views, section 2.2.2; AwTV for finite delta,
@@ -507,7 +507,10 @@ def asd_pocs(geo: Geometry, angles, b, niter: int, blocksize: int = 1, kind: str
          dtvg <- dtvg alpha_red;
       5. lam <- lam lam_red.
     The paper names the algorithm and its parameters without the steps;
-    these follow Sidky and Pan's published description."""
+    these follow Sidky and Pan's published description.  When `trace` is a
+    list, one dict per iteration is appended with the quantities of steps
+    2-5: dp, dd, dg, the TV step length used (dtvg) and the data step used
+    (lam)."""
     angles = _angles(angles)
     b = _f64(b)
     x = np.zeros(geo.nVoxel) if x0 is None else _f64(x0).copy()
@@ -537,6 +540,8 @@ def asd_pocs(geo: Geometry, angles, b, niter: int, blocksize: int = 1, kind: str
             if gn > 0:
                 x = x - dtvg * g / gn
         dg = float(np.linalg.norm(x - x_tv))
+        if trace is not None:
+            trace.append({"dp": dp, "dd": dd, "dg": dg, "dtvg": dtvg, "lam": lam})
         if dg > rmax * dp and dd > eps_data:
             dtvg *= alpha_red
         lam *= lam_red

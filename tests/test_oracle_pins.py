@@ -809,3 +809,79 @@ def test_pnp_cgls_identity_denoiser_restarts_cgls(orc):
         g2 = float(np.vdot(s, s))
         p, gam = s + (g2 / gam) * p, g2
     assert np.max(np.abs(x - xx)) < 1e-10 * np.max(np.abs(xx))
+
+
+# ------------------------------------------- ASD-POCS step-size control
+_POCS_GEO = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(10, 10),
+                     dDetector=(1.4, 1.4))
+_POCS = dict(blocksize=2, kind="interp", lam=1.0, lam_red=0.9, alpha=0.02, alpha_red=0.7, ng=5, rmax=0.5,
+             eps_data=3.0, delta=math.inf, eps_tv=1e-8)
+
+
+def _check_asd_pocs_trace(orc, asd_pocs, niter=8):
+    """Re-derives ASD-POCS (Sidky and Pan's steps, the paper's POCS class
+    of section 2.2 with its OS form of section 2.2.2) from pinned pieces --
+    one OS-SART pass (oracle.os_sart) and the TV gradient (oracle.awtv_grad)
+    -- and checks every iteration's dp, dd, dg, TV step length and data step
+    against the trace of `asd_pocs`, then the image.  The step length starts
+    at alpha dp and is multiplied by alpha_red after an iteration whose TV
+    change dg exceeds rmax dp while the data residual dd is above eps_data;
+    lam shrinks by lam_red every iteration.  Returns the decisions taken."""
+    geo, p = _POCS_GEO, _POCS
+    ang = synth.circular_angles(6)
+    xt = np.zeros(geo.nVoxel)
+    xt[2:6, 2:7, 1:6] = 1.0
+    xt[3:5, 3:5, 3:5] = 2.0
+    b = orc.forward(geo, ang, xt, "interp")
+    trace = []
+    got = asd_pocs(geo, ang, b, niter, trace=trace, **p)
+    assert len(trace) == niter
+    x = np.zeros(geo.nVoxel)
+    lam, dtvg, events = p["lam"], None, []
+    for k in range(niter):
+        x_prev = x
+        x = orc.os_sart(geo, ang, b, 1, p["blocksize"], lam=lam, nonneg=True, kind="interp", x0=x)
+        dd = float(np.linalg.norm(orc.forward(geo, ang, x, "interp") - b))
+        dp = float(np.linalg.norm(x - x_prev))
+        if dtvg is None:
+            dtvg = p["alpha"] * dp
+        x_tv = x
+        for _ in range(p["ng"]):
+            g = orc.awtv_grad(x, p["delta"], p["eps_tv"])
+            x = x - dtvg * g / np.linalg.norm(g)
+        dg = float(np.linalg.norm(x - x_tv))
+        t = trace[k]
+        for name, want in (("dp", dp), ("dd", dd), ("dg", dg), ("dtvg", dtvg), ("lam", lam)):
+            assert abs(t[name] - want) <= 1e-10 * abs(want), (k, name, t[name], want)
+        over, noisy = dg > p["rmax"] * dp, dd > p["eps_data"]
+        events.append((over, noisy))
+        if over and noisy:
+            dtvg *= p["alpha_red"]
+        lam *= p["lam_red"]
+    assert _rel(got, x) < 1e-10
+    return events
+
+
+def test_asd_pocs_step_size_trace(orc):
+    events = _check_asd_pocs_trace(orc, orc.asd_pocs)
+    # the rule fires, holds below rmax, and holds above rmax once the data
+    # residual is within eps_data: every branch is taken before the last
+    # iteration, so a wrong decision shows in a later step length
+    assert (True, True) in events[:-1]
+    assert any(not over for over, _ in events[:-1])
+    assert (True, False) in events[:-1]
+
+
+@pytest.mark.parametrize("old,new", [
+    ("if dg > rmax * dp and dd > eps_data:", "if dg < rmax * dp and dd > eps_data:"),
+    ("if dg > rmax * dp and dd > eps_data:", "if dg > rmax * dp:"),
+    ("if dg > rmax * dp and dd > eps_data:", "if dg > rmax * dg and dd > eps_data:"),
+    ("dtvg = alpha * dp", "dtvg = alpha * dd"),
+    ("        lam *= lam_red\n", "        lam *= 1.0\n"),
+    ("dtvg *= alpha_red", "dtvg *= lam_red"),
+], ids=["inverted", "no-data-tolerance", "dg-vs-dg", "start-from-dd", "no-lam-decay", "wrong-factor"])
+def test_asd_pocs_trace_pin_catches_planted_mistakes(orc, old, new):
+    from _mutants import py_oracle_mutant
+    mutant = py_oracle_mutant(orc.asd_pocs, old, new)
+    with pytest.raises(AssertionError):
+        _check_asd_pocs_trace(orc, mutant)
