@@ -130,6 +130,11 @@ def num_threads() -> int:
     return int(_L().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """OpenMP thread count of the following oracle calls."""
+    _L().orc_set_num_threads(ctypes.c_int(int(n)))
+
+
 # ------------------------------------------------------------- operators
 def forward(geo: Geometry, angles, vol, kind: str = "siddon") -> np.ndarray:
     """b = A x (the paper's linear model, section 2.1, Eq. 1)."""
@@ -259,7 +264,7 @@ def fdk(geo: Geometry, angles, proj, wang: bool = False) -> np.ndarray:
 
 
 # ----------------------------------------------------- iterative methods
-def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, mask=None):
+def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, mask=None, callback=None):
     """CGLS (Hestenes & Stiefel; the paper's Krylov methods, section 2.2.1).
 
     x0 = 0; r = b - A x0; s = A^T r; p = s; gamma = |s|^2.  Each iteration:
@@ -267,6 +272,7 @@ def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, 
     r -= alpha q; s = A^T r; gamma' = |s|^2; beta = gamma'/gamma;
     p = s + beta p.  Records |r_k| (the residual-norm history) and, given a
     ground truth, |x_gt - x_k| and the PSNR (the error-norm history).
+    callback(k, x), when given, sees the iterate after iteration k (1-based).
     """
     b = _f64(b)
     x = np.zeros(geo.nVoxel)
@@ -295,6 +301,8 @@ def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, 
         if x_gt is not None:
             hist["err"].append(float(np.linalg.norm((x - x_gt).ravel())))
             hist["psnr"].append(psnr(x, x_gt, mask))
+        if callback is not None:
+            callback(k + 1, x)
     return x, hist
 
 
@@ -365,7 +373,7 @@ def _recip0(a):
 
 
 def os_sart(geo: Geometry, angles, b, niter: int, blocksize: int, lam: float = 1.0, nonneg: bool = True,
-            kind: str = "interp", x0=None):
+            kind: str = "interp", x0=None, callback=None):
     """OS-SART (ordered-subset step of section 2.2.2 with the row/column
     length normalisation of SART).  The OS step is printed with the residual
     as (A_s x - b_s); read as (b_s - A_s x), the descent direction.
@@ -373,7 +381,8 @@ def os_sart(geo: Geometry, angles, b, niter: int, blocksize: int, lam: float = 1
     Per block s: W = 1 / (A_s 1), V = 1 / (A_s^T 1) (0 where the sum is 0);
     x <- x + lam * V (A_s^T (W (b_s - A_s x))); then x <- max(x, 0) if nonneg.
     One iteration is one pass over all blocks.  SART is blocksize 1, SIRT
-    one block.
+    one block.  callback(k, x), when given, sees the iterate after pass k
+    (1-based).
     """
     angles = _angles(angles)
     b = _f64(b)
@@ -384,13 +393,15 @@ def os_sart(geo: Geometry, angles, b, niter: int, blocksize: int, lam: float = 1
         a = angles[idx]
         W.append(_recip0(forward(geo, a, np.ones(geo.nVoxel), kind)))
         V.append(_recip0(backward(geo, a, np.ones((len(idx),) + tuple(geo.nDetector)), kind)))
-    for _ in range(niter):
+    for it in range(niter):
         for s, idx in enumerate(blocks):
             a = angles[idx]
             e = b[idx] - forward(geo, a, x, kind)
             x = x + lam * V[s] * backward(geo, a, W[s] * e, kind)
             if nonneg:
                 x = np.maximum(x, 0.0)
+        if callback is not None:
+            callback(it + 1, x)
     return x
 
 
@@ -546,6 +557,80 @@ def asd_pocs(geo: Geometry, angles, b, niter: int, blocksize: int = 1, kind: str
             dtvg *= alpha_red
         lam *= lam_red
     return x
+
+
+# ------------------------------------------------------ curved detectors
+def curved_pixel_centres(geo: Geometry, theta: float, cd) -> np.ndarray:
+    """World positions (nv, nu, 3) of a curved detector's pixel centres for
+    the view at gantry angle theta (curved detectors, section 2.4).
+
+    With e_s = (cos t, sin t, 0) pointing at the source S = DSO e_s,
+    u_hat = (-sin t, cos t, 0) and the flat detector's centre D = S - DSD e_s,
+    the arc's axis runs through A = D + R e_s parallel to z (R = cd.radius),
+    and pixel (iv, iu), at arc length s = (iu + 1/2 - nu/2) du + off_u and
+    height v = (iv + 1/2 - nv/2) dv + off_v, sits at
+    A - R cos(s / R) e_s + R sin(s / R) u_hat + v z."""
+    c, sn = math.cos(theta), math.sin(theta)
+    es = np.array([c, sn, 0.0])
+    uh = np.array([-sn, c, 0.0])
+    zh = np.array([0.0, 0.0, 1.0])
+    S = geo.DSO * es
+    A = S - geo.DSD * es + cd.radius * es
+    nv, nu = cd.nDetector
+    s = (np.arange(nu) + 0.5 - nu / 2) * cd.dDetector[1] + cd.offDetector[1]
+    v = (np.arange(nv) + 0.5 - nv / 2) * cd.dDetector[0] + cd.offDetector[0]
+    phi = s / cd.radius
+    row = A[None, :] - cd.radius * np.cos(phi)[:, None] * es[None, :] + cd.radius * np.sin(phi)[:, None] * uh[None, :]
+    return row[None, :, :] + v[:, None, None] * zh[None, None, :]
+
+
+def flatten_curved(geo: Geometry, cd, curved) -> np.ndarray:
+    """The flattening transformation of the paper's curved-detector support
+    (section 2.4): projections measured on the curved detector `cd` (views,
+    nv_c, nu_c), resampled onto the flat detector of `geo`.
+
+    Flat pixel (iv, iu) at (u_f, v_f) (the geometry's pixel centres) defines
+    the ray from the source through D + u_f u_hat + v_f z.  In the plane
+    normal to z, the point at parameter t along that ray (t = 1 on the flat
+    detector) lies at (DSD - R - t DSD) e_s + t u_f u_hat from the arc's axis;
+    the ray meets the cylinder where that distance is R, i.e. at the
+    positive root of
+        (DSD^2 + u_f^2) t^2 - 2 DSD (DSD - R) t + (DSD - R)^2 - R^2 = 0
+    (one positive root: R > DSD / 2 keeps the source inside the cylinder).
+    There the arc length is s = R atan2(t u_f, t DSD - DSD + R) and the
+    height v = t v_f.  The flat value is the curved projection at (s, v),
+    bilinear between curved pixel centres and 0 outside the curved detector:
+    the ray is the same, so its line integral is carried over unchanged.
+    The geometry repeats for every view of a circular orbit."""
+    curved = _f64(curved)
+    if not cd.radius > geo.DSD / 2:
+        raise ValueError("the arc radius must exceed DSD / 2")
+    nv, nu = geo.nDetector
+    R, DSD = cd.radius, geo.DSD
+    uf = (np.arange(nu) + 0.5 - nu / 2) * geo.dDetector[1] + geo.offDetector[1]
+    vf = (np.arange(nv) + 0.5 - nv / 2) * geo.dDetector[0] + geo.offDetector[0]
+    a = DSD * DSD + uf * uf
+    b = -2.0 * DSD * (DSD - R)
+    c = (DSD - R) ** 2 - R * R
+    t = (-b + np.sqrt(b * b - 4.0 * a * c)) / (2.0 * a)
+    s = R * np.arctan2(t * uf, t * DSD - DSD + R)                 # (nu,)
+    vc = t[None, :] * vf[:, None]                                  # (nv, nu)
+    nvc, nuc = cd.nDetector
+    cu = (s - cd.offDetector[1]) / cd.dDetector[1] + nuc / 2 - 0.5
+    cv = (vc - cd.offDetector[0]) / cd.dDetector[0] + nvc / 2 - 0.5
+    iu0 = np.floor(cu).astype(np.int64)
+    iv0 = np.floor(cv).astype(np.int64)
+    fu = cu - iu0
+    fv = cv - iv0
+    out = np.zeros((curved.shape[0], nv, nu))
+    for du_ in (0, 1):
+        for dv_ in (0, 1):
+            ju = np.broadcast_to(iu0 + du_, (nv, nu))
+            jv = iv0 + dv_
+            w = (fu if du_ else 1.0 - fu)[None, :] * (fv if dv_ else 1.0 - fv)
+            ok = (ju >= 0) & (ju < nuc) & (jv >= 0) & (jv < nvc)
+            out += np.where(ok, w, 0.0)[None] * curved[:, np.clip(jv, 0, nvc - 1), np.clip(ju, 0, nuc - 1)]
+    return out
 
 
 # --------------------------------------------------------------- metrics

@@ -857,3 +857,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the following calls (timing runs); n < 1 is ignored. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

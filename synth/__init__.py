@@ -28,7 +28,7 @@ __all__ = [
     "Geometry", "Ellipsoid", "WORKLOADS", "workload", "circular_angles",
     "head_phantom", "random_ellipsoids", "voxelize", "gaussian_texture",
     "uniform_volume", "uniform_projections", "poisson_log_data", "normal_weights",
-    "bf16_values", "textured_phantom",
+    "bf16_values", "textured_phantom", "CurvedDetector",
 ]
 
 
@@ -71,6 +71,22 @@ class Geometry:
     def iso_fov_radius(self) -> float:
         """Radius of the volume's inscribed cylinder (the FOV mask), mm."""
         return 0.5 * min(self.nVoxel[1] * self.dVoxel[1], self.nVoxel[2] * self.dVoxel[2])
+
+
+@dataclasses.dataclass(frozen=True)
+class CurvedDetector:
+    """A cylindrically curved detector (the paper's curved detectors, section
+    2.4: the pixel rows follow an arc in the fan direction, straight along v).
+
+    The arc passes through the flat detector's centre, with its axis parallel
+    to v at distance `radius` from that centre towards the source; radius =
+    DSD puts every pixel of a row at the same distance from the source.  u
+    pixel positions are arc lengths from the centre.
+    """
+    nDetector: Tuple[int, int]          # (nv, nu)
+    dDetector: Tuple[float, float]      # (dv, du) mm, du along the arc
+    radius: float                       # mm
+    offDetector: Tuple[float, float] = (0.0, 0.0)   # (v, u) mm, u along the arc
 
 
 def circular_angles(n: int) -> np.ndarray:
