@@ -28,26 +28,31 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# published MI355X peaks
+# MI355X datasheet figures: HBM3E bandwidth, and the non-packed FP32 vector
+# issue rate derived from the unit counts (256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.32 T lane-instructions/s; the 157.3 TFLOP/s vector peak
+# counts packed FMAs as 4 flops per lane-instruction, and this library is
+# built without packed FP32)
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_VALU_TLI = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# algorithmic FP32 flops per unit of work (add/mul/sub/floor = 1, fma = 2):
-#   interpolated A, per sample: position 3 fma (6), floor 3, fraction 3,
-#     1 - f 3, seven lerps (mul + fma = 3 each) 21, accumulate 1      = 37
-#   interpolated A^T, per sample: position 6, floor 3, fraction 3, 1 - f 3,
-#     eight corner weights (2 mul each) 16, times y 8, accumulate 8    = 47
-#   Siddon A, per segment: 3-way min 2, clip min 1, length sub 1,
-#     accumulate fma 2, exit compare 1, next plane add 1 + fma 2       = 10
-#   Siddon A^T, per segment: the same with one multiply by y           = 11
-#   FDK backprojection, per voxel-view update: v position fma 2, floor 1,
-#     fraction 1, 1 - f 1, two u-lerps 6, v-lerp 3, weight fma 2       = 16
-FLOPS = {"interp_fwd": 37, "interp_bwd": 47, "siddon_fwd": 10, "siddon_bwd": 11, "fdk_bp": 16}
+# algorithmic VALU lane-instructions per unit of work (minimum inner loops,
+# non-packed):
+#   Siddon A and A^T, per plane crossing: 2 compare/min to pick the next
+#     plane, 1 sub for the length, 1 FMA to accumulate, 1 add to advance
+#     alpha, 1 integer index step                                      = 6
+#   interpolated A, per sample: 3 advance, 6 floor/fract, 7 lerps x 2,
+#     1 accumulate                                                     = 24
+#   interpolated A^T, per sample: 3 advance, 6 fract, 15 to form the 8
+#     tent weights, 8 FMA scatters                                     = 32
+#   FDK backprojection, per voxel-view update: 3 incremental numerators,
+#     1 rcp, 2 mul, 2 weight, 4 floor/fract, 3 lerps x 2               = 18
+INSTR = {"siddon_fwd": 6, "siddon_bwd": 6, "interp_fwd": 24, "interp_bwd": 32, "fdk_bp": 18}
 
 # source file of each timed kernel (the HBM traffic recorded for a kernel in
 # profiles/traffic.json is used only while that file is unchanged)
 KERNEL_SOURCE = {"interp_fwd": "forward.hip", "siddon_fwd": "forward.hip", "interp_bwd": "backward.hip",
-                 "siddon_bwd": "backward.hip", "fdk_bp": "fdk.hip"}
+                 "siddon_bwd": "backward.hip", "fdk_bp": "fdk.hip", "fdk_filter": "fdk.hip"}
 
 
 def _sha256(path):
@@ -161,22 +166,111 @@ def work_units(geo, nviews, sample_views=16):
     return samples * scale, segments * scale
 
 
+def _median_ms(torch, stream, fn, reps=10, warm=3):
+    for _ in range(warm):
+        fn()
+    evs = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def measure_ceilings(torch, dev):
+    """The two ceilings of the roofline, measured on this GPU: HBM bytes per
+    second of a streaming copy of 2 GiB (read + write), and non-packed FP32
+    lane-instructions per second of an FMA loop (16 independent chains per
+    lane, 8192 workgroups of 256 lanes).  Medians of 10 launches."""
+    import ctypes
+    from paper_2412_10129_amd import _lib as L
+    lib = L.lib()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    n = 1 << 29
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    t_copy = _median_ms(torch, stream, lambda: L.check(lib.ctmi_ceiling_copy(
+        ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(c.data_ptr()), n, sp)))
+    if not bool(torch.equal(a, c)):
+        raise RuntimeError("ceiling copy is wrong")
+    del a, c
+    blocks, iters = 8192, 4096
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    t_fma = _median_ms(torch, stream, lambda: L.check(lib.ctmi_ceiling_fma(
+        ctypes.c_void_p(out.data_ptr()), blocks, iters, sp)))
+    lanes = blocks * 256 * int(lib.ctmi_ceiling_fma_per_lane(iters))
+    return {"hbm_GBs": round(8.0 * n / (t_copy / 1e3) / 1e9, 1), "copy_ms": round(t_copy, 4),
+            "valu_T_lane_instr_s": round(lanes / (t_fma / 1e3) / 1e12, 3), "fma_ms": round(t_fma, 4),
+            "datasheet_hbm_GBs": PEAK_HBM_GBS, "datasheet_valu_T_lane_instr_s": round(PEAK_VALU_TLI, 3)}
+
+
+def roof(t_ms, instr=0.0, nbytes=0.0, ceil=None):
+    """Binding-roof fraction max(bytes / BW, instr / R) / t, with the measured
+    ceilings and with the datasheet ones, and the bound it names."""
+    t = t_ms / 1e3
+    ent = {"ms": round(t_ms, 3)}
+    if instr:
+        ent["T_lane_instr_s"] = round(instr / t / 1e12, 3)
+    if nbytes:
+        ent["GB/s_alg"] = round(nbytes / t / 1e9, 1)
+    for tag, bw, r in (("", ceil["hbm_GBs"] if ceil else None, ceil["valu_T_lane_instr_s"] if ceil else None),
+                       ("_datasheet", PEAK_HBM_GBS, PEAK_VALU_TLI)):
+        if bw is None:
+            continue
+        tb, ti = nbytes / (bw * 1e9), instr / (r * 1e12)
+        ent["frac_roof" + tag] = round(max(tb, ti) / t, 4)
+        if not tag:
+            ent["bound"] = "alu" if ti >= tb else "hbm"
+    return ent
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(geo, angles, x, y, kind):
-    """The FP64 oracle on one view of the workload: forward and backward."""
+    """The FP64 oracle on a sample of the workload: A and A^T on the first two
+    views with every host thread, and on the first view with one thread
+    (work is uniform over the views of a circular orbit, so the rate scales
+    to the full 720 views)."""
     import oracle
     oracle._L()
-    a1 = angles[:1]
     x64 = x.astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.forward(geo, a1, x64, kind)
-    t1 = time.perf_counter()
-    oracle.backward(geo, a1, y[:1].astype(np.float64), kind)
-    t2 = time.perf_counter()
+    nt = oracle.num_threads()
+
+    def timed(nviews):
+        a = angles[:nviews]
+        t0 = time.perf_counter()
+        oracle.forward(geo, a, x64, kind)
+        t1 = time.perf_counter()
+        oracle.backward(geo, a, y[:nviews].astype(np.float64), kind)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+    fa, fb = timed(2)
+    oracle.set_num_threads(1)
+    try:
+        sa, sb = timed(1)
+    finally:
+        oracle.set_num_threads(nt)
     upd = float(np.prod(geo.nVoxel))
-    return {"value": 2 * upd / (t2 - t0), "unit": "voxel-view updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 {kind} A and A^T, 1 of {len(angles)} views of the 512^3 workload "
-                      f"(A {t1 - t0:.1f} s, A^T {t2 - t1:.1f} s)"}
+    return {"value": 2 * 2 * upd / (fa + fb), "unit": "voxel-view updates/s", "cores": nt, "kind": "oracle",
+            "sample": f"FP64 {kind} A and A^T on 2 of {len(angles)} views of the 512^3 workload with {nt} threads "
+                      f"(A {fa:.1f} s, A^T {fb:.1f} s); rate scales to all views",
+            "single_thread": {"value": 2 * upd / (sa + sb), "sample": f"1 view, 1 thread (A {sa:.1f} s, "
+                                                                      f"A^T {sb:.1f} s)"},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
 def main():
@@ -195,6 +289,9 @@ def main():
     ap.add_argument("--profile-summary", metavar="DB",
                     help="only print markdown tables of a rocprofv3 results database and exit")
     ap.add_argument("--top", type=int, default=12, help="kernels listed by --profile-summary")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="run each rated kernel once on the workload (after a 1 GiB calibration copy) and exit: "
+                         "the program profiled for kernel traces and counters")
     args = ap.parse_args()
     if args.profile_summary:
         print(profile_summary(args.profile_summary, top=args.top))
@@ -249,6 +346,38 @@ def main():
                                          ws.numel() * 8, ops._stream()))
 
     dot_into(s, slot(0, 0))
+    if args.profile_run:
+        import ctypes
+        from paper_2412_10129_amd import algs as AL
+        lib = ops.L.lib()
+        cal = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        cal2 = torch.empty_like(cal)
+        ops.L.check(lib.ctmi_ceiling_copy(ctypes.c_void_p(cal.data_ptr()), ctypes.c_void_p(cal2.data_ptr()), cal.numel(),
+                                          ops._stream()))
+        torch.cuda.synchronize()
+        del cal, cal2
+        gn = ops.dot(s, s)
+        runs = [
+            ("siddon_fwd", lambda: plan.forward(x, out=q, kind="siddon")),
+            ("siddon_bwd", lambda: plan.backproject(b, out=s, kind="siddon")),
+            ("interp_fwd", lambda: plan.forward(x, out=q, kind="interp")),
+            ("interp_bwd", lambda: plan.backproject(b, out=s, kind="interp")),
+            ("fdk_filter", lambda: plan.fdk_filter(b, out=q)),
+            ("fdk_bp", lambda: plan.backproject(b, out=s, kind="fdk")),
+            ("awtv_grad", lambda: ops.awtv_grad(x, out=p, delta=0.5)),
+            ("tv_step", lambda: ops.tv_step(xs, p, gn, 1e-3)),
+            ("cgls_xr", lambda: ops.cgls_xr(xs, p, r, q, slot(0, 0), slot(0, 1), slot(0, 2), ws)),
+            ("cgls_p", lambda: ops.cgls_p(p, s, slot(0, 0), slot(1, 0))),
+            ("dot_proj", lambda: dot_into(q, slot(1, 3))),
+            ("em_ratio", lambda: ops.em_ratio(b, q, q)),
+            ("em_update", lambda: ops.em_update(xs, p, s)),
+        ]
+        for name, fn in runs:
+            fn()
+            torch.cuda.synchronize()
+            print(f"[bench] profile run: {name}", flush=True)
+        print("[bench] profile run done", flush=True)
+        return
     ev_f0, ev_f1, ev_b0, ev_b1 = [], [], [], []
     it = [0]
 
@@ -297,20 +426,26 @@ def main():
           f"|r|^2 {h[0, 2]:.6g} / {h[1, 2]:.6g}", flush=True)
 
     samples, segments = work_units(geo, nviews)
-    units = {"interp_fwd": samples, "interp_bwd": samples, "siddon_fwd": segments, "siddon_bwd": segments}
+    units = {"interp_fwd": samples, "interp_bwd": samples, "siddon_fwd": segments, "siddon_bwd": segments,
+             "fdk_bp": upd}
+    proj_bytes = 4.0 * (float(np.prod(geo.nVoxel)) + float(b.numel()))   # read one, write the other, once
+    print("[bench] measuring the HBM and VALU ceilings ...", flush=True)
+    ceil = measure_ceilings(torch, dev)
+    print(f"[bench] ceilings: {ceil}", flush=True)
     kf, kb = f"{kind}_fwd", f"{kind}_bwd"
     dominant, t_dom = (kb, t_bwd) if t_bwd >= t_fwd else (kf, t_fwd)
-    fl = FLOPS[dominant] * units[dominant]
-    ach = fl / (t_dom / 1e3) / 1e12
-    roofline = {"bound": "alu", "kernel": dominant, "achieved": round(ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+    li = INSTR[dominant] * units[dominant]
+    ach = li / (t_dom / 1e3) / 1e12
+    rd = roof(t_dom, li, proj_bytes, ceil)
+    roofline = {"bound": "alu", "kernel": dominant, "achieved": round(ach, 3), "peak": round(PEAK_VALU_TLI, 3),
+                "unit": "T VALU lane-instr/s", "frac": round(ach / PEAK_VALU_TLI, 4),
                 "traffic": recorded_traffic(dominant),
-                "work_units": units[dominant], "flops_per_unit": FLOPS[dominant],
-                "avg_launch_ms": round(float(t_dom), 3)}
+                "peak_measured": ceil["valu_T_lane_instr_s"], "frac_measured": rd["frac_roof"],
+                "work_units": units[dominant], "lane_instr_per_unit": INSTR[dominant],
+                "alg_bytes": proj_bytes, "avg_launch_ms": round(float(t_dom), 3), "ceilings": ceil}
 
     breakdown = {}
     if not args.no_breakdown:
-        fl_fdk = float(np.prod(geo.nVoxel)) * nviews
         ops_list = [
             ("siddon_fwd", lambda: plan.forward(x, out=q, kind="siddon")),
             ("siddon_bwd", lambda: plan.backproject(b, out=s, kind="siddon")),
@@ -320,22 +455,12 @@ def main():
             ("fdk_bp", lambda: plan.backproject(b, out=s, kind="fdk")),
         ]
         for name, fn in ops_list:
-            fn()
-            ea = torch.cuda.Event(enable_timing=True)
-            eb = torch.cuda.Event(enable_timing=True)
-            ea.record(stream)
-            for _ in range(2):
-                fn()
-            eb.record(stream)
-            torch.cuda.synchronize()
-            t = ea.elapsed_time(eb) / 2
-            ent = {"ms": round(t, 3)}
+            t = _median_ms(torch, stream, fn, reps=3, warm=1)
             if name == "fdk_filter":
-                ent["GB/s"] = round(2 * 4 * b.numel() / (t / 1e3) / 1e9, 1)
+                ent = roof(t, 0.0, 8.0 * b.numel(), ceil)
             else:
+                ent = roof(t, INSTR[name] * units[name], proj_bytes, ceil)
                 ent["updates/s"] = float(f"{upd / (t / 1e3):.4g}")
-                u = units.get(name, fl_fdk)
-                ent["TFLOP/s"] = round(FLOPS[name] * u / (t / 1e3) / 1e12, 3)
             breakdown[name] = ent
             print(f"[bench] {name}: {ent}", flush=True)
 
@@ -353,19 +478,16 @@ def main():
             ("tv_step", lambda: O.tv_step(xs, s, gn, 1e-3), 12.0 * nvox),
             ("em_ratio", lambda: O.em_ratio(b, q, q), 12.0 * b.numel()),
             ("em_update", lambda: O.em_update(xs, bps, bps), 16.0 * nvox),
+            # CGLS vector steps of the timed iteration: x += a p, r -= a q with
+            # |r|^2; p = s + b p; one FP64 norm of a projection-sized vector
+            ("cgls_xr", lambda: ops.cgls_xr(xs, p, r, q, slot(0, 0), slot(0, 1), slot(0, 2), ws),
+             12.0 * nvox + 12.0 * b.numel()),
+            ("cgls_p", lambda: ops.cgls_p(bps, s, slot(0, 0), slot(1, 0)), 12.0 * nvox),
+            ("dot_proj", lambda: dot_into(q, slot(1, 3)), 4.0 * b.numel()),
         ]
         for name, fn, nbytes in extra:
-            fn()
-            ea = torch.cuda.Event(enable_timing=True)
-            eb = torch.cuda.Event(enable_timing=True)
-            ea.record(stream)
-            for _ in range(3):
-                fn()
-            eb.record(stream)
-            torch.cuda.synchronize()
-            t = ea.elapsed_time(eb) / 3
-            ent = {"ms": round(t, 3), "GB/s": round(nbytes / (t / 1e3) / 1e9, 1),
-                   "frac_hbm": round(nbytes / (t / 1e3) / 8e12, 3)}
+            t = _median_ms(torch, stream, fn, reps=3, warm=1)
+            ent = roof(t, 0.0, nbytes, ceil)
             breakdown[name] = ent
             print(f"[bench] {name}: {ent}", flush=True)
         del xs, bps
@@ -418,12 +540,12 @@ def main():
         # prior inside CGLS against plain CGLS (a bounded training run)
         print("[bench] learned prior: pairs, training, PnP-CGLS vs CGLS ...", flush=True)
         from paper_2412_10129_amd import learned as LN
-        learned = LN.quick_benchmark(log=lambda m: print(f"[bench] {m}", flush=True))
+        learned = LN.quick_benchmark(log=lambda m: print(f"[bench] {m}", flush=True), weights=LN.WEIGHTS)
         print(f"[bench] learned: {learned['wall_s']} s", flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on one view ...", flush=True)
+        print("[bench] timing the FP64 oracle on a sample of views ...", flush=True)
         cpu = cpu_baseline(geo, angles, x_h, y_h, kind)
 
     out = {

@@ -24,21 +24,22 @@
  *     per-axis array of the detector (v, u).
  *
  * Memory and streams: all array arguments are DEVICE pointers, 4-byte
- * aligned, owned by the caller.  The library never allocates or frees per
- * call and keeps no pointer after a call returns.  Every call is
- * asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
- * returns after enqueueing its kernels.  A plan owns one device allocation
- * made on the device that is current when the plan is created: the per-view
- * geometry and filter tables, and the interpolated adjoint's brick-shell
- * buffer (553 floats per 16x16x8 voxel brick, about 27 % of the volume's
- * size).  Calls must run with that device current, and interpolated
- * backprojections that share a plan must not run concurrently (they share
- * the shell buffer); every other call may.
+ * aligned, owned by the caller, and so are the workspaces that some calls
+ * take (ctmi_workspace_size gives their size).  The library never allocates
+ * or frees per call and keeps no pointer after a call returns.  Every call
+ * is asynchronous on `stream` (a hipStream_t; NULL = the null stream) and
+ * returns after enqueueing its kernels.  A plan owns one small device
+ * allocation made on the device that is current when the plan is created:
+ * the per-view geometry tables (256 bytes per view) and the ramp filter's
+ * tables.  Plans are immutable after creation, so calls on one plan may run
+ * concurrently on different streams, each with its own workspace; calls
+ * must run with the plan's device current.
  *
  * Errors: every call returns CTMI_OK (0) or a negative code; argument checks
  * happen before anything is enqueued, so a failing call has no effect.
  * ctmi_last_error() returns a thread-local message for the last failure.
- * Faults inside kernels surface asynchronously through the HIP runtime.
+ * Faults inside kernels surface asynchronously through the HIP runtime, on a
+ * later call or through ctmi_stream_check.
  */
 #ifndef CTMI_H
 #define CTMI_H
@@ -90,6 +91,17 @@ typedef struct {
 } ctmi_geometry;
 
 typedef struct ctmi_plan ctmi_plan;
+
+/* Operations, for ctmi_workspace_size. */
+enum ctmi_op {
+    CTMI_OP_FORWARD_SIDDON = 0,
+    CTMI_OP_FORWARD_INTERP = 1,
+    CTMI_OP_BACKPROJECT_SIDDON = 2,
+    CTMI_OP_BACKPROJECT_INTERP = 3,
+    CTMI_OP_BACKPROJECT_FDK = 4,
+    CTMI_OP_FDK_FILTER = 5,
+    CTMI_OP_FOV_SQ_ERR = 6
+};
 
 /* Thread-local description of the last error (never NULL). */
 const char* ctmi_last_error(void);
@@ -155,6 +167,21 @@ int ctmi_plan_create_views(const ctmi_geometry* geo, const ctmi_view* views, int
  * call using the plan may be in flight.  NULL is accepted. */
 int ctmi_plan_destroy(ctmi_plan* plan);
 
+/* Device workspace (bytes) that operation `op` (enum ctmi_op) needs on this
+ * plan, for any view range; 0 when it needs none.  The interpolated
+ * backprojector needs 553 floats per 16x16x8 voxel brick (about 27 % of
+ * the volume's size: the bricks' upper shells, handed to their neighbours);
+ * the FOV error needs ctmi_reduce_workspace_bytes.  Errors: CTMI_EINVAL for
+ * a NULL plan or bytes, or an unknown op.  No GPU work. */
+int ctmi_workspace_size(const ctmi_plan* plan, int op, size_t* bytes);
+
+/* Reports errors that the device raised asynchronously: CTMI_EHIP (with the
+ * runtime's message) when the stream (a hipStream_t; NULL = the null
+ * stream) is in an error state or the runtime holds an error from an
+ * earlier launch (which this call clears), else CTMI_OK.  Does not wait for
+ * the stream. */
+int ctmi_stream_check(void* stream);
+
 /* proj = A vol for views [view0, view0 + nviews) of the plan.
  * vol: [nz][ny][nx]; proj: [nviews][nv][nu] holding only those views.
  * projector: CTMI_SIDDON or CTMI_INTERP.  Overwrites proj.
@@ -165,12 +192,22 @@ int ctmi_forward(const ctmi_plan* plan, int projector, const float* vol, float* 
 /* vol = beta * vol + B proj for views [view0, view0 + nviews).
  * bp = CTMI_BP_SIDDON / CTMI_BP_INTERP: B is the exact transpose A^T of the
  * matching projector (the adjoint the Krylov methods of section 2.2.1
- * require), computed brick-by-brick with one writer per voxel.
+ * require), computed brick-by-brick with one writer per voxel.  A voxel
+ * that a ray with a NaN or infinite value reaches (a Siddon piece of
+ * positive length, or a corner of an interpolation sample) is set to NaN;
+ * the other voxels get the sum over the finite values.
  * bp = CTMI_BP_FDK: B is the FDK backprojector (DSO/U)^2-weighted bilinear
  * detector sampling (section 2.1, FDK).  beta = 0 ignores the old contents
- * of vol (NaNs included). */
+ * of vol (NaNs included).
+ * ws: device workspace of ws_bytes >= ctmi_workspace_size(plan,
+ * CTMI_OP_BACKPROJECT_INTERP) bytes, 16-byte aligned, for bp =
+ * CTMI_BP_INTERP (contents need not be initialised; the call overwrites
+ * them, so concurrent calls need distinct workspaces); ignored (may be NULL)
+ * otherwise.  Errors: CTMI_EINVAL (plan, range, pointers, beta not finite,
+ * FDK on a non-circular plan gives CTMI_EUNSUPPORTED), CTMI_EWORKSPACE
+ * (workspace missing or too small). */
 int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0,
-                     int64_t nviews, float beta, void* stream);
+                     int64_t nviews, float beta, void* ws, size_t ws_bytes, void* stream);
 
 /* FDK filtering of views [view0, view0 + nviews): out = scale * tau *
  * (h * (w_cos * w_wang * proj)) row by row, h the Ram-Lak kernel on the iso
@@ -259,6 +296,50 @@ int ctmi_em_update(float* x, const float* v, const float* bp, int64_t n, void* s
  * ws: ctmi_reduce_workspace_bytes(nvox) bytes. */
 int ctmi_fov_sq_err(const ctmi_plan* plan, const float* x, const float* gt, double* out, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------ curved detectors -- */
+/* A cylindrically curved detector (section 2.4 on geometric flexibility:
+ * curved detectors, taken in through a flattening transformation).  The
+ * pixel rows follow an arc whose axis is parallel to v and passes at
+ * distance `radius` from the flat detector's centre towards the source
+ * (radius = DSD: every pixel of a row at the same distance from the
+ * source).  u positions and du are arc lengths. */
+typedef struct {
+    int64_t nDetector[2];  /* (nv, nu) */
+    double dDetector[2];   /* (dv, du) mm, du along the arc */
+    double offDetector[2]; /* (v, u) mm, u along the arc */
+    double radius;         /* mm, finite and > DSD / 2 */
+} ctmi_curved_detector;
+
+/* Flattening transformation: flat = the curved projections `curved`
+ * ([nviews][cd.nv][cd.nu], views [view0, view0 + nviews) of the plan)
+ * resampled onto the plan's flat detector ([nviews][nv][nu]).  Flat pixel
+ * (u, v) takes the curved projection where its ray meets the cylinder: at
+ * parameter t along source -> flat pixel, the positive root of
+ * (DSD^2 + u^2) t^2 - 2 DSD (DSD - R) t + (DSD - R)^2 - R^2 = 0, i.e. arc
+ * length R atan2(t u, t DSD - DSD + R) and height t v; bilinear between
+ * curved pixel centres, 0 outside the curved detector.  The line integral
+ * along a ray does not depend on where the ray meets a detector, so the
+ * flattened projections feed every flat-geometry operator (FDK, the
+ * iterative solvers).  Circular-orbit plans only (CTMI_EUNSUPPORTED
+ * otherwise); flat must not alias curved.  Errors: CTMI_EINVAL (sizes,
+ * pitches, offsets, radius <= DSD / 2, pointers), CTMI_EOVERFLOW (nu > 65536
+ * or 2^28 pixels or more). */
+int ctmi_flatten_curved(const ctmi_plan* plan, const ctmi_curved_detector* cd, const float* curved, float* flat,
+                        int64_t view0, int64_t nviews, void* stream);
+
+/* --------------------------------------------------------- ceilings -- */
+/* Measurement kernels that compute nothing of the reconstruction: the two
+ * machine ceilings that the projector, filter and vector kernels are rated
+ * against.  ctmi_ceiling_copy copies n floats (n a multiple of 4; src and dst
+ * 16-byte aligned device arrays, not overlapping) with 16-byte accesses: 8 n
+ * bytes of HBM traffic.  ctmi_ceiling_fma runs blocks x 256 lanes, each
+ * executing ctmi_ceiling_fma_per_lane(iters) independent non-packed FP32
+ * fused multiply-adds, and writes one float per lane to out (blocks x 256
+ * device floats).  Errors: CTMI_EINVAL for bad sizes or pointers. */
+int ctmi_ceiling_copy(const float* src, float* dst, int64_t n, void* stream);
+int64_t ctmi_ceiling_fma_per_lane(int iters);
+int ctmi_ceiling_fma(float* out, int blocks, int iters, void* stream);
 
 #ifdef __cplusplus
 }

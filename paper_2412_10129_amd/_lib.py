@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "libctmi.so")
 CTMI_OK, CTMI_EINVAL, CTMI_EUNSUPPORTED, CTMI_EOVERFLOW, CTMI_EWORKSPACE, CTMI_EHIP = 0, -1, -2, -3, -4, -5
 CTMI_SIDDON, CTMI_INTERP = 0, 1
 CTMI_BP_SIDDON, CTMI_BP_INTERP, CTMI_BP_FDK = 0, 1, 2
+(CTMI_OP_FORWARD_SIDDON, CTMI_OP_FORWARD_INTERP, CTMI_OP_BACKPROJECT_SIDDON, CTMI_OP_BACKPROJECT_INTERP,
+ CTMI_OP_BACKPROJECT_FDK, CTMI_OP_FDK_FILTER, CTMI_OP_FOV_SQ_ERR) = range(7)
 
 c_i64, c_f, c_d, c_p, c_int = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
 
@@ -48,6 +50,21 @@ class CtmiView(ctypes.Structure):
                 ("COR", c_d), ("rotDetector", c_d * 3)]
 
 
+class CtmiCurvedDetector(ctypes.Structure):
+    _fields_ = [("nDetector", c_i64 * 2), ("dDetector", c_d * 2), ("offDetector", c_d * 2), ("radius", c_d)]
+
+
+def curved_struct(cd) -> CtmiCurvedDetector:
+    """From any object with nDetector (nv, nu), dDetector (dv, du), radius and
+    optionally offDetector (v, u)."""
+    c = CtmiCurvedDetector()
+    c.nDetector = (c_i64 * 2)(*[int(v) for v in cd.nDetector])
+    c.dDetector = (c_d * 2)(*[float(v) for v in cd.dDetector])
+    c.offDetector = (c_d * 2)(*[float(v) for v in getattr(cd, "offDetector", (0.0, 0.0))])
+    c.radius = float(cd.radius)
+    return c
+
+
 def view_structs(views):
     """ctmi_view records from a per-view description: any object with
     per-view arrays angles (n, 3) z1 y1 z2, DSO, DSD (n,), offOrigin (n, 3),
@@ -74,7 +91,9 @@ _SIGS = {
     "ctmi_plan_create_views": (c_int, [c_p, c_p, c_i64, ctypes.POINTER(c_p)]),
     "ctmi_plan_destroy": (c_int, [c_p]),
     "ctmi_forward": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),
-    "ctmi_backproject": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_f, c_p]),
+    "ctmi_backproject": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_f, c_p, ctypes.c_size_t, c_p]),
+    "ctmi_workspace_size": (c_int, [c_p, c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "ctmi_stream_check": (c_int, [c_p]),
     "ctmi_fdk_filter": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),
     "ctmi_reduce_workspace_bytes": (ctypes.c_size_t, [c_i64]),
     "ctmi_dot": (c_int, [c_p, c_p, c_i64, c_p, c_p, ctypes.c_size_t, c_p]),
@@ -89,6 +108,10 @@ _SIGS = {
     "ctmi_tv_step": (c_int, [c_p, c_p, c_i64, c_p, c_f, c_p]),
     "ctmi_em_update": (c_int, [c_p, c_p, c_p, c_i64, c_p]),
     "ctmi_fov_sq_err": (c_int, [c_p, c_p, c_p, c_p, c_p, ctypes.c_size_t, c_p]),
+    "ctmi_flatten_curved": (c_int, [c_p, c_p, c_p, c_p, c_i64, c_i64, c_p]),
+    "ctmi_ceiling_copy": (c_int, [c_p, c_p, c_i64, c_p]),
+    "ctmi_ceiling_fma_per_lane": (c_i64, [c_int]),
+    "ctmi_ceiling_fma": (c_int, [c_p, c_int, c_int, c_p]),
     # learned prior (ctmi_unet.h)
     "ctmi_conv3d_bf16_fwd": (c_int, [c_int] * 4 + [c_p, c_int, c_int, c_p, c_int, c_int, c_p, c_p, c_int, c_int, c_p,
                                                    c_int, c_p]),

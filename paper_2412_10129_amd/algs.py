@@ -268,7 +268,7 @@ def asd_pocs(plan: Plan, b: torch.Tensor, niter: int, blocksize: int = 1, kind: 
 
 def pnp_cgls(plan: Plan, b: torch.Tensor, niter: int, denoiser, every: int = 5, ratio: float = 1.05,
              kind: str = "interp", x_gt: Optional[torch.Tensor] = None, data_range: Optional[float] = None,
-             timing: bool = False):
+             timing: bool = False, keep: Optional[list] = None):
     """CGLS with a plug-and-play denoiser step (the learned prior inside the
     Krylov solver of section 2.2.1).
 
@@ -281,7 +281,9 @@ def pnp_cgls(plan: Plan, b: torch.Tensor, niter: int, denoiser, every: int = 5, 
     Returns (x, hist): per-iteration residual norms, the proposals' ratios and
     decisions, with x_gt the FOV squared errors (and PSNR given data_range),
     and with timing=True the per-iteration solver time in ms (GPU events
-    around each iteration's kernels, error bookkeeping excluded).
+    around each iteration's kernels, error bookkeeping excluded).  When
+    `keep` is a list, a device copy of every iterate is appended to it
+    (outside the timed region), for judging them afterwards.
     """
     dev = plan.device
     ws = ops._ws(dev)
@@ -340,6 +342,8 @@ def pnp_cgls(plan: Plan, b: torch.Tensor, niter: int, denoiser, every: int = 5, 
             ev.append((e0, e1))
         if x_gt is not None:
             plan.fov_sq_err(x, x_gt, err[k])
+        if keep is not None:
+            keep.append(x.clone())
     h = sc.cpu().numpy()
     resid = np.sqrt(h[:, 1])
     for k, v in resid_from_proposal.items():

@@ -180,18 +180,30 @@ __device__ __forceinline__ int owner(const int* pre, int it)
     return lo;
 }
 
-// Fixed-point scale for one (brick, group of views): the largest power of
-// two s with s * cmax * maxy <= 2^30, cmax a bound on a single contribution's
-// matrix factor (one Siddon chord, or one interpolation sample's ds), so
-// every contribution a y_i fits an int32 with 2^-30 of the largest one as
-// resolution.  Returns s and writes 1/s.
-__device__ __forceinline__ float fixed_scale(float cmax, float maxy, float* inv)
+// Fixed-point scale for one (brick, group of views) or one round: the
+// exponent e of the largest power of two (up to exact powers of two) with
+// 2^e cmax m <= 2^30, where cmax bounds a single contribution's matrix
+// factor (one Siddon chord, or K samples of ds) and m > 0 is the group's
+// largest |y| or the round's sum of |y| (finite values only).  Formed from
+// the operands' exponents, so neither a product nor a quotient can
+// overflow or underflow: with cmax = a 2^ec and m = b 2^em (a, b in
+// [1/2, 1)), 2^(30 - ec - em) cmax m = 2^30 a b < 2^30, and one more
+// power of two fits when a b < 1/2.  Contributions are scaled by 2^e and
+// the integer sums by 2^-e with ldexp (exact), so the fixed point works at
+// every magnitude of y that FP32 holds.
+__device__ __forceinline__ int fixed_exp(float cmax, float m)
 {
-    int e;
-    (void)__builtin_frexpf(0x1p30f / (cmax * maxy), &e);
-    e = min(max(e - 1, -120), 120);
-    *inv = __builtin_ldexpf(1.0f, -e);
-    return __builtin_ldexpf(1.0f, e);
+    int ec, em;
+    const float a = __builtin_frexpf(cmax, &ec);
+    const float b = __builtin_frexpf(m, &em);
+    return 30 - ec - em + (a * b < 0.5f ? 1 : 0);
+}
+
+// |y| for finite y, 0 for NaN and infinities (those rays are handled by
+// k_nonfinite after the accumulation)
+__device__ __forceinline__ float finite_or_zero(float y)
+{
+    return __builtin_fabsf(y) <= 0x1.fffffep127f ? y : 0.0f;
 }
 
 // A contribution q (|q| <= 2^30 by the choice of scale) as a sign-extended
@@ -275,7 +287,7 @@ __device__ __forceinline__ float group_max(GroupLds& G, const float* __restrict_
     for (int c = threadIdx.x; c < total; c += blockDim.x) {
         int g, iu, iv;
         group_pixel(G, c, g, iu, iv);
-        m = fmaxf(m, fabsf(proj[((int64_t)(k + g) * det.nv + iv) * det.nu + iu]));
+        m = fmaxf(m, fabsf(finite_or_zero(proj[((int64_t)(k + g) * det.nv + iv) * det.nu + iu])));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
@@ -290,7 +302,7 @@ __device__ __forceinline__ float group_max(GroupLds& G, const float* __restrict_
 // cleared by the same thread; cells outside the brick that no flush reads
 // are never cleared (they only collect discarded contributions).
 template <typename Acc>
-__device__ __forceinline__ void flush_view(Acc* acc, int px, int py, int pad, float inv, float own[OWN])
+__device__ __forceinline__ void flush_view(Acc* acc, int px, int py, int pad, int e, float own[OWN])
 {
 #pragma unroll
     for (int m = 0; m < OWN; ++m) {
@@ -299,7 +311,7 @@ __device__ __forceinline__ void flush_view(Acc* acc, int px, int py, int pad, fl
         Acc* c = acc + ((lz + pad) * py + (ly + pad)) * px + (lx + pad);
         const Acc a = *c;
         *c = 0;
-        own[m] = __builtin_fmaf((float)(long long)a, inv, own[m]);
+        own[m] += __builtin_ldexpf((float)(long long)a, -e);
     }
 }
 
@@ -377,12 +389,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         // footprints; 32-bit cells: one scale per round (below)
         const float maxy = SID_ACC32 ? 1.0f : group_max(G, proj, det, k, npx);
         if (!(maxy > 0.0f)) continue;
-        float inv;
-        float scale = SID_ACC32 ? 0.0f : fixed_scale(cmax, maxy, &inv);
+        int ex = SID_ACC32 ? 0 : fixed_exp(cmax, maxy);
         for (int p0 = 0; p0 < npx; p0 += 256) {
             const int p = round_pixel<CTMI_BWD_SID_SPREAD != 0>(p0);
             int cnt = 0;
-            float yr = 0.0f, yl_ = 0.0f;   // this ray's y, and y times its world length
+            float yr = 0.0f, yl_ = 0.0f;   // this ray's y (finite, else 0), and its world length
             if (p < npx) {
                 int gv, iu, iv;
                 group_pixel(G, p, gv, iu, iv);
@@ -419,8 +430,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                         t_a1[tid] = amax;
                         t_c0[tid] = c0 * 4 + dom;
                         t_nc[tid] = nc;
-                        yr = pk[(int64_t)iv * det.nu + iu];
-                        yl_ = yr * world_length(d, v);
+                        yr = finite_or_zero(pk[(int64_t)iv * det.nu + iu]);
+                        yl_ = world_length(d, v);
                     }
                 }
             }
@@ -435,9 +446,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     __syncthreads();
                     continue;
                 }
-                scale = fixed_scale(cmax, ysum, &inv);
+                ex = fixed_exp(cmax, ysum);
             }
-            if (cnt > 0) t_y[tid] = yl_ * scale;
+            // scaled before the length factor: |y 2^e| <= 2^30 / cmax
+            if (cnt > 0) t_y[tid] = __builtin_ldexpf(yr, ex) * yl_;
             t_pre[tid] = off;
             fill_item_map(imap, off, cnt);
             __syncthreads();
@@ -507,12 +519,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             __syncthreads();
             if (SID_ACC32) {
                 // 32-bit cells hold one round's sums (bounded by the scale)
-                flush_view(acc, BX, BY, 0, inv, own);
+                flush_view(acc, BX, BY, 0, ex, own);
                 __syncthreads();
             }
         }
         if (!SID_ACC32) {
-            flush_view(acc, BX, BY, 0, inv, own);
+            flush_view(acc, BX, BY, 0, ex, own);
             __syncthreads();
         }
     }
@@ -556,7 +568,7 @@ __device__ __forceinline__ void halo_slot(int h, int& lx, int& ly, int& lz)
 // shell cells -> per-thread FP32 registers, clearing them (accumulator
 // origin at the brick corner minus one voxel)
 template <typename Acc>
-__device__ __forceinline__ void flush_shell(Acc* acc, float inv, float hown[NH])
+__device__ __forceinline__ void flush_shell(Acc* acc, int e, float hown[NH])
 {
 #pragma unroll
     for (int m = 0; m < NH; ++m) {
@@ -567,7 +579,7 @@ __device__ __forceinline__ void flush_shell(Acc* acc, float inv, float hown[NH])
             Acc* c = acc + ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1);
             const Acc a = *c;
             *c = 0;
-            hown[m] = __builtin_fmaf((float)(long long)a, inv, hown[m]);
+            hown[m] += __builtin_ldexpf((float)(long long)a, -e);
         }
     }
 }
@@ -745,7 +757,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_B
             }
             if (lane == 0) wsumf[wid] = ya;
             __syncthreads();
-            const float ysum = (wsumf[0] + wsumf[1]) + (wsumf[2] + wsumf[3]);
+            float ysum = (wsumf[0] + wsumf[1]) + (wsumf[2] + wsumf[3]);
+            if (!(ysum <= 0x1.fffffep127f)) {
+                // a NaN or an infinity among the round's values (those rays
+                // add nothing here; k_nonfinite marks their voxels), or a
+                // finite sum past FLT_MAX: sum again over the finite values
+                // (block-uniform branch)
+                float yb = 0.0f;
+#pragma unroll
+                for (int h = 0; h < RPT; ++h) {
+                    yr[h] = finite_or_zero(yr[h]);
+                    yb += fabsf(yr[h]);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) yb += __shfl_xor(yb, o, 64);
+                __syncthreads();
+                if (lane == 0) wsumf[wid] = yb;
+                __syncthreads();
+                ysum = (wsumf[0] + wsumf[1]) + (wsumf[2] + wsumf[3]);
+            }
             if (!(ysum > 0.0f)) {
                 // nothing to add: keep the LDS sums of this pass alive until
                 // every thread has read them
@@ -769,14 +799,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_B
             // one cell's round sum is at most cmax sum_r |y_r| (cmax: K
             // samples of ds, K the most samples of one ray inside a
             // 2x2x2-voxel support)
-            float inv;
-            const float scale = fixed_scale(cmax, ysum, &inv);
+            // (a sum of finite values can only overflow when some |y| is
+            // near FLT_MAX; 512 values of at most 2^128 bound it by 2^137)
+            const int ex = ysum <= 0x1.fffffep127f ? fixed_exp(cmax, ysum) : fixed_exp(cmax, 0x1p127f) - 10;
 #pragma unroll
             for (int h = 0; h < RPT; ++h) {
                 const int sl = tid + 256 * h;
                 t_pre[sl] = off[h];
                 if (cnt[h] > 0) {
-                    t_a[sl].w = yr[h] * ds * scale;
+                    // scaled before ds: |y 2^e| <= 2^30 / cmax and cmax >= ds
+                    t_a[sl].w = __builtin_ldexpf(yr[h], ex) * ds;
                     const int e = min(off[h] + cnt[h], IMAPCAP);
                     for (int i = off[h]; i < e; ++i) imap[i] = (unsigned short)sl;
                 }
@@ -837,8 +869,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_B
             // scale).  No barrier is needed after it: the next round's
             // atomics come after two more barriers, and nothing before them
             // touches the accumulator.
-            flush_shell(acc, inv, hown);
-            flush_view(acc, HX, HY, 1, inv, own);
+            flush_shell(acc, ex, hown);
+            flush_view(acc, HX, HY, 1, ex, own);
         }
     }
     store_owned(vol, own, v, x0, y0, z0, beta);
@@ -879,6 +911,83 @@ __global__ void k_halo_add(float* __restrict__ vol, const float* __restrict__ sh
     if (X || Y || Z) vol[i] += add;
 }
 
+// Non-finite projection values.  The adjoints above add finite values only
+// (a NaN or infinite y_i counts as 0 there, which keeps the fixed-point
+// scales finite); this pass then sets every voxel that such a ray reaches to
+// NaN, since a_ij y_i is NaN or infinite there.  A voxel is reached when the
+// Siddon walk gives it a piece of positive length, or when it is a corner of
+// an interpolation sample inside the interpolant's support.  Rays are taken
+// grid-stride, one per thread; a ray with a finite value costs one coalesced
+// load.
+template <bool SIDDON>
+__global__ void __launch_bounds__(256) k_nonfinite(const float* __restrict__ proj, float* __restrict__ vol,
+                                                   const ViewGeo64* __restrict__ tab64, int view0, int64_t nrays,
+                                                   VolDims v, DetDims det, float ds, float inv_ds)
+{
+    const int64_t npix = (int64_t)det.nu * det.nv;
+    const float qnan = __builtin_nanf("");
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrays; i += (int64_t)gridDim.x * blockDim.x) {
+        if (finite_or_zero(proj[i]) == proj[i]) continue;
+        const int view = (int)(i / npix);
+        const int pix = (int)(i - (int64_t)view * npix);
+        const int iu = pix % det.nu, iv = pix / det.nu;
+        const ViewGeo64& g = tab64[view0 + view];
+        if (SIDDON) {
+            float S[3], d[3], amin, amax;
+            siddon_ray(g, iu, iv, v, S, d, amin, amax);
+            const SiddonAxis ax = siddon_axis(S[0], d[0]), ay = siddon_axis(S[1], d[1]), az = siddon_axis(S[2], d[2]);
+            bool hit = slab_clip(ax, S[0], 0.0f, (float)v.nx, amin, amax);
+            hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, amax);
+            hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, amax);
+            if (!hit || !(amin < amax)) continue;
+            int ix = ordered_cell(ax, S[0], d[0], amin, 0, v.nx);
+            int iy = ordered_cell(ay, S[1], d[1], amin, 0, v.ny);
+            int iz = ordered_cell(az, S[2], d[2], amin, 0, v.nz);
+            float anx = plane_alpha(ax, (float)(ix + (ax.step > 0)));
+            float any = plane_alpha(ay, (float)(iy + (ay.step > 0)));
+            float anz = plane_alpha(az, (float)(iz + (az.step > 0)));
+            float acur = amin;
+            for (int step = 0; step < v.nx + v.ny + v.nz + 3; ++step) {
+                const float an = fminf(anx, fminf(any, anz));
+                if (fminf(an, amax) > acur) vol[((int64_t)iz * v.ny + iy) * v.nx + ix] = qnan;
+                if (an >= amax) break;
+                acur = an;
+                if (an == anx) {
+                    ix += ax.step;
+                    if (ix < 0 || ix >= v.nx) break;
+                    anx = plane_alpha(ax, (float)(ix + (ax.step > 0)));
+                } else if (an == any) {
+                    iy += ay.step;
+                    if (iy < 0 || iy >= v.ny) break;
+                    any = plane_alpha(ay, (float)(iy + (ay.step > 0)));
+                } else {
+                    iz += az.step;
+                    if (iz < 0 || iz >= v.nz) break;
+                    anz = plane_alpha(az, (float)(iz + (az.step > 0)));
+                }
+            }
+        } else {
+            InterpRay r;
+            if (!interp_ray(g, iu, iv, v, ds, inv_ds, r)) continue;
+            for (int k = r.k0; k <= r.k1; ++k) {
+                float p[3];
+                interp_pos(r, k, p);
+                if (!(p[0] > -1.0f && p[0] < (float)v.nx && p[1] > -1.0f && p[1] < (float)v.ny && p[2] > -1.0f &&
+                      p[2] < (float)v.nz))
+                    continue;
+                const int fx = (int)__builtin_floorf(p[0]), fy = (int)__builtin_floorf(p[1]),
+                          fz = (int)__builtin_floorf(p[2]);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int cx = fx + (c & 1), cy = fy + ((c >> 1) & 1), cz = fz + (c >> 2);
+                    if (cx >= 0 && cx < v.nx && cy >= 0 && cy < v.ny && cz >= 0 && cz < v.nz)
+                        vol[((int64_t)cz * v.ny + cy) * v.nx + cx] = qnan;
+                }
+            }
+        }
+    }
+}
+
 BrickMap brick_map(const Plan& p)
 {
     BrickMap m;
@@ -888,7 +997,26 @@ BrickMap brick_map(const Plan& p)
     return m;
 }
 
+template <bool SIDDON>
+hipError_t launch_nonfinite(const Plan& p, const float* proj, float* vol, int64_t view0, int64_t nviews, hipStream_t s)
+{
+    const int64_t nrays = nviews * (int64_t)p.det.nu * p.det.nv;
+    if (nrays == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((nrays + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_nonfinite<SIDDON>, dim3((unsigned)blocks), dim3(256), 0, s, proj, vol, p.d_views64,
+                       (int)view0, nrays, p.vol, p.det, p.ds, 1.0f / p.ds);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int64_t adjoint_bricks(const Plan& p)
+{
+    const BrickMap m = brick_map(p);
+    return (int64_t)m.nbx * m.nby * m.nbz;
+}
+
+size_t interp_adjoint_ws_bytes(const Plan& p) { return sizeof(float) * (size_t)adjoint_bricks(p) * HALO_SLOTS; }
 
 hipError_t launch_backward_siddon(const Plan& p, const float* proj, float* vol, int64_t view0, int64_t nviews,
                                   float beta, hipStream_t s)
@@ -897,21 +1025,24 @@ hipError_t launch_backward_siddon(const Plan& p, const float* proj, float* vol, 
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_siddon, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
                        (int)nviews, p.vol, p.det, m, beta, SID_ACC32 ? p.round_siddon : p.entry_siddon);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_nonfinite<true>(p, proj, vol, view0, nviews, s);
 }
 
 hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, int64_t view0, int64_t nviews,
-                                  float beta, hipStream_t s)
+                                  float beta, float* shell, hipStream_t s)
 {
     const BrickMap m = brick_map(p);
     const unsigned blocks = (unsigned)m.nbx * m.nby * m.nbz;
     hipLaunchKernelGGL(k_backward_interp, dim3(blocks), dim3(256), 0, s, proj, vol, p.d_views, p.d_views64, (int)view0,
-                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.round_interp, p.d_halo);
+                       (int)nviews, p.vol, p.det, m, beta, p.ds, p.round_interp, shell);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)p.vol.nx * p.vol.ny * p.vol.nz;
-    hipLaunchKernelGGL(k_halo_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vol, p.d_halo, p.vol, m);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_halo_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vol, shell, p.vol, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_nonfinite<false>(p, proj, vol, view0, nviews, s);
 }
 
 }  // namespace ctmi

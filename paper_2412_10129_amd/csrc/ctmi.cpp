@@ -397,8 +397,6 @@ int ctmi::api_fail(int code, const char* fmt, ...)
 
 int ctmi::api_hip(hipError_t e, const char* what) { return hip_fail(e, what); }
 
-struct ctmi_plan : Plan {};
-
 extern "C" {
 
 const char* ctmi_last_error(void) { return g_err; }
@@ -482,13 +480,8 @@ static int create_plan(const ctmi_geometry* geo, const double* angles, const ctm
     const size_t t64b = sizeof(ctmi::ViewGeo64) * (size_t)nviews;
     const size_t hb = sizeof(float) * (size_t)L;
     const size_t wb = sizeof(float) * (size_t)L;  // L/2 float2
-    // upper shells of the interpolated adjoint's voxel bricks
-    const size_t nbricks = (size_t)((p->vol.nx + CTMI_BWD_BX - 1) / CTMI_BWD_BX) *
-                           ((p->vol.ny + CTMI_BWD_BY - 1) / CTMI_BWD_BY) * ((p->vol.nz + CTMI_BWD_BZ - 1) / CTMI_BWD_BZ);
-    const size_t sb = sizeof(float) * nbricks * CTMI_HALO_SLOTS;
-    const size_t sof = (tb + t64b + hb + wb + 255) / 256 * 256;
     char* mem = nullptr;
-    e = hipMalloc(reinterpret_cast<void**>(&mem), sof + sb);
+    e = hipMalloc(reinterpret_cast<void**>(&mem), tb + t64b + hb + wb);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "hipMalloc(plan tables)");
@@ -497,7 +490,6 @@ static int create_plan(const ctmi_geometry* geo, const double* angles, const ctm
     p->d_views64 = reinterpret_cast<ctmi::ViewGeo64*>(mem + tb);
     p->d_filter = reinterpret_cast<float*>(mem + tb + t64b);
     p->d_twiddle = reinterpret_cast<float2*>(mem + tb + t64b + hb);
-    p->d_halo = reinterpret_cast<float*>(mem + sof);
     if ((e = hipMemcpy(p->d_views, t.data(), tb, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_views64, t64.data(), t64b, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_filter, Hbr.data(), hb, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -557,8 +549,41 @@ int ctmi_forward(const ctmi_plan* plan, int projector, const float* vol, float* 
                : launched(ctmi::launch_forward_interp(*plan, vol, proj, view0, nviews, s), "forward (interpolated)");
 }
 
-int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
-                     float beta, void* stream)
+static size_t op_workspace(const Plan& p, int op)
+{
+    switch (op) {
+    case CTMI_OP_BACKPROJECT_INTERP: return ctmi::interp_adjoint_ws_bytes(p);
+    case CTMI_OP_FOV_SQ_ERR: return ctmi::reduce_ws_bytes();
+    default: return 0;
+    }
+}
+
+int ctmi_workspace_size(const ctmi_plan* plan, int op, size_t* bytes)
+{
+    int rc;
+    if ((rc = check_plan(plan))) return rc;
+    if (!bytes) return fail(CTMI_EINVAL, "bytes is NULL");
+    if (op < CTMI_OP_FORWARD_SIDDON || op > CTMI_OP_FOV_SQ_ERR) return fail(CTMI_EINVAL, "unknown operation %d", op);
+    *bytes = op_workspace(*plan, op);
+    return CTMI_OK;
+}
+
+int ctmi_stream_check(void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamQuery(s);
+    if (e != hipSuccess && e != hipErrorNotReady) return hip_fail(e, "stream");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "device");
+    return CTMI_OK;
+}
+
+}  // extern "C"
+
+// Checks shared by the backprojection entry points (everything except the
+// workspace).
+int ctmi::check_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
+                            float beta)
 {
     int rc;
     if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
@@ -570,17 +595,40 @@ int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vo
     if ((rc = check_ptr(vol, "vol")) || (nviews > 0 && (rc = check_ptr(proj, "proj"))) ||
         (rc = check_device(plan)))
         return rc;
+    return CTMI_OK;
+}
+
+int ctmi::run_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
+                          float beta, float* ws, void* stream)
+{
     hipStream_t s = static_cast<hipStream_t>(stream);
     // nviews == 0 still applies vol = beta * vol (proj is not read)
     switch (bp) {
     case CTMI_BP_SIDDON:
         return launched(ctmi::launch_backward_siddon(*plan, proj, vol, view0, nviews, beta, s), "backproject (Siddon)");
     case CTMI_BP_INTERP:
-        return launched(ctmi::launch_backward_interp(*plan, proj, vol, view0, nviews, beta, s),
+        return launched(ctmi::launch_backward_interp(*plan, proj, vol, view0, nviews, beta, ws, s),
                         "backproject (interpolated)");
     default:
         return launched(ctmi::launch_backward_fdk(*plan, proj, vol, view0, nviews, beta, s), "backproject (FDK)");
     }
+}
+
+extern "C" {
+
+int ctmi_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
+                     float beta, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc;
+    if ((rc = ctmi::check_backproject(plan, bp, proj, vol, view0, nviews, beta))) return rc;
+    if (bp == CTMI_BP_INTERP) {
+        const size_t need = ctmi::interp_adjoint_ws_bytes(*plan);
+        if (!ws) return fail(CTMI_EWORKSPACE, "the interpolated backprojector needs a workspace of %zu bytes", need);
+        if (reinterpret_cast<uintptr_t>(ws) % 16 != 0) return fail(CTMI_EINVAL, "workspace is not 16-byte aligned");
+        if (ws_bytes < need)
+            return fail(CTMI_EWORKSPACE, "workspace of %zu bytes is below the %zu required", ws_bytes, need);
+    }
+    return ctmi::run_backproject(plan, bp, proj, vol, view0, nviews, beta, static_cast<float*>(ws), stream);
 }
 
 int ctmi_fdk_filter(const ctmi_plan* plan, int wang, const float* proj, float* out, int64_t view0, int64_t nviews,
@@ -741,6 +789,62 @@ int ctmi_fov_sq_err(const ctmi_plan* plan, const float* x, const float* gt, doub
     if (!out) return fail(CTMI_EINVAL, "out is NULL");
     return launched(ctmi::launch_fov_sq_err(*plan, x, gt, out, static_cast<double*>(ws), static_cast<hipStream_t>(stream)),
                     "fov_sq_err");
+}
+
+/* -------------------------------------------------- curved detectors -- */
+int ctmi_flatten_curved(const ctmi_plan* plan, const ctmi_curved_detector* cd, const float* curved, float* flat,
+                        int64_t view0, int64_t nviews, void* stream)
+{
+    int rc;
+    if ((rc = check_plan(plan)) || (rc = check_views(plan, view0, nviews))) return rc;
+    if (!cd) return fail(CTMI_EINVAL, "curved detector is NULL");
+    if (!plan->circular) return fail(CTMI_EUNSUPPORTED, "flattening needs a circular-orbit plan");
+    for (int a = 0; a < 2; ++a) {
+        if (cd->nDetector[a] < 1) return fail(CTMI_EINVAL, "curved detector sizes must be >= 1");
+        if (!(cd->dDetector[a] > 0.0) || !std::isfinite(cd->dDetector[a]))
+            return fail(CTMI_EINVAL, "curved detector pitch must be finite and > 0");
+        if (!std::isfinite(cd->offDetector[a])) return fail(CTMI_EINVAL, "curved detector offset is not finite");
+    }
+    if (cd->nDetector[1] > 65536 || (double)cd->nDetector[0] * (double)cd->nDetector[1] >= 268435456.0)
+        return fail(CTMI_EOVERFLOW, "curved detector must hold nu <= 65536 and fewer than 2^28 pixels");
+    if (!std::isfinite(cd->radius) || !(cd->radius > 0.5 * plan->geo.DSD))
+        return fail(CTMI_EINVAL, "arc radius must be finite and > DSD / 2 (the source inside the cylinder)");
+    if (nviews == 0) return CTMI_OK;
+    if ((rc = check_ptr(curved, "curved")) || (rc = check_ptr(flat, "flat")) || (rc = check_device(plan))) return rc;
+    if (static_cast<const void*>(curved) == static_cast<const void*>(flat))
+        return fail(CTMI_EINVAL, "flat must not alias curved");
+    ctmi::CurvedDet c;
+    c.nv = (int)cd->nDetector[0];
+    c.nu = (int)cd->nDetector[1];
+    c.dv = cd->dDetector[0];
+    c.du = cd->dDetector[1];
+    c.ov = cd->offDetector[0];
+    c.ou = cd->offDetector[1];
+    c.R = cd->radius;
+    return launched(ctmi::launch_flatten_curved(*plan, c, curved, flat, nviews, static_cast<hipStream_t>(stream)),
+                    "flatten_curved");
+}
+
+/* ------------------------------------------------------- ceilings -- */
+int ctmi_ceiling_copy(const float* src, float* dst, int64_t n, void* stream)
+{
+    int rc;
+    if ((rc = check_n(n))) return rc;
+    if (n % 4) return fail(CTMI_EINVAL, "n must be a multiple of 4");
+    if (n == 0) return CTMI_OK;
+    if (!src || !dst || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(CTMI_EINVAL, "src and dst must be 16-byte aligned device pointers");
+    return launched(ctmi::launch_stream_copy(src, dst, n, static_cast<hipStream_t>(stream)), "ceiling copy");
+}
+
+int64_t ctmi_ceiling_fma_per_lane(int iters) { return (int64_t)ctmi::fma_loop_chains() * (int64_t)iters; }
+
+int ctmi_ceiling_fma(float* out, int blocks, int iters, void* stream)
+{
+    int rc;
+    if ((rc = check_ptr(out, "out"))) return rc;
+    if (blocks < 1 || iters < 1) return fail(CTMI_EINVAL, "blocks and iters must be >= 1");
+    return launched(ctmi::launch_fma_loop(out, blocks, iters, static_cast<hipStream_t>(stream)), "ceiling fma");
 }
 
 }  // extern "C"

@@ -89,8 +89,12 @@ struct Plan {
     float entry_siddon;   // largest single adjoint term factor, Siddon (one chord, mm)
     float round_interp;   // most one ray adds to one adjoint cell per unit y: K ds (mm)
     float round_siddon;   // the same for Siddon: one chord (mm)
-    float* d_halo;        // interpolated adjoint: CTMI_HALO_SLOTS floats per voxel brick
 };
+
+// Voxel bricks of the matched adjoints along each axis, and the bytes of the
+// interpolated adjoint's workspace (CTMI_HALO_SLOTS floats per brick).
+int64_t adjoint_bricks(const Plan& p);
+size_t interp_adjoint_ws_bytes(const Plan& p);
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_forward_siddon(const Plan& p, const float* vol, float* proj, int64_t view0, int64_t nviews,
@@ -100,7 +104,7 @@ hipError_t launch_forward_interp(const Plan& p, const float* vol, float* proj, i
 hipError_t launch_backward_siddon(const Plan& p, const float* proj, float* vol, int64_t view0, int64_t nviews,
                                   float beta, hipStream_t s);
 hipError_t launch_backward_interp(const Plan& p, const float* proj, float* vol, int64_t view0, int64_t nviews,
-                                  float beta, hipStream_t s);
+                                  float beta, float* shell, hipStream_t s);
 hipError_t launch_backward_fdk(const Plan& p, const float* proj, float* vol, int64_t view0, int64_t nviews,
                                float beta, hipStream_t s);
 hipError_t launch_fdk_filter(const Plan& p, int wang, const float* proj, float* out, int64_t view0,
@@ -182,6 +186,31 @@ hipError_t launch_unet_adam(float* w, float* m, float* v, const float* g, int64_
                             float inv_sqrt_bc2, float eps, hipStream_t s);
 hipError_t launch_unet_pack_conv3(const float* w, int cout, int cin, uint16_t* wf, uint16_t* wd, hipStream_t s);
 hipError_t launch_unet_to_bf16(const float* a, int64_t n, uint16_t* out, hipStream_t s);
+
+// curved detectors: flat (plan) and curved pixel grids, mm
+struct FlatDet {
+    int nu, nv;
+    double du, dv, ou, ov;
+};
+struct CurvedDet {
+    int nu, nv;
+    double du, dv, ou, ov;  // du, ou along the arc
+    double R;               // arc radius
+};
+hipError_t launch_flatten_curved(const Plan& p, const CurvedDet& c, const float* curved, float* flat, int64_t nviews,
+                                 hipStream_t s);
+
+// measurement ceilings
+hipError_t launch_stream_copy(const float* src, float* dst, int64_t n, hipStream_t s);
+int fma_loop_chains();
+hipError_t launch_fma_loop(float* out, int blocks, int iters, hipStream_t s);
+
+// backprojection entry points: argument checks (all but the workspace) and
+// the launch with a checked workspace
+int check_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
+                      float beta);
+int run_backproject(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0, int64_t nviews,
+                    float beta, float* ws, void* stream);
 
 // error reporting shared by the entry points (thread-local message)
 int api_fail(int code, const char* fmt, ...);
@@ -408,3 +437,6 @@ __device__ __forceinline__ void interp_pos(const InterpRay& r, int k, float p[3]
 #endif  // __HIPCC__
 
 }  // namespace ctmi
+
+// The opaque plan of the C ABI is the library's Plan.
+struct ctmi_plan : ctmi::Plan {};

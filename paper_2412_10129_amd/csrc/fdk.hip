@@ -248,10 +248,16 @@ __device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y
 // tw[k] = exp(-2 pi i k / L), k < L/2; a radix-2 stage of span S uses
 // tw[j L / (2 S)] for the pair at offset j of its block.
 //
+// Each pass reads its inputs through `ld(i)` and writes its outputs through
+// `st(i, v)` (i the row position), so the first forward pass can read the
+// weighted detector row straight from global memory, the last forward pass
+// can apply the filter response as it stores, and the last inverse pass can
+// write the filtered row straight to global memory.
+//
 // DIF pass over stages S, S/2, S/4 (E = S/4): butterfly t < L/8 takes
 // elements i0 + k E, k < 8, i0 = (t / E) 2S + t mod E.
-template <bool P>
-__device__ __forceinline__ void dif8(float2* buf, const float2* tw, int L, int S)
+template <class LD, class ST>
+__device__ __forceinline__ void dif8(const float2* tw, int L, int S, LD ld, ST st)
 {
     const int E = S >> 2, ts1 = L / (2 * S);
     for (int t = threadIdx.x; t < (L >> 3); t += blockDim.x) {
@@ -259,7 +265,7 @@ __device__ __forceinline__ void dif8(float2* buf, const float2* tw, int L, int S
         const int i0 = ((t - j) << 3) + j;
         float2 x[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = buf[pad<P>(i0 + k * E)];
+        for (int k = 0; k < 8; ++k) x[k] = ld(i0 + k * E);
         float2 y[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -271,38 +277,49 @@ __device__ __forceinline__ void dif8(float2* buf, const float2* tw, int L, int S
         for (int q = 0; q < 8; q += 4) {
             const float2 z0 = cadd(y[q], y[q + 2]), z2 = cmul(csub(y[q], y[q + 2]), c0);
             const float2 z1 = cadd(y[q + 1], y[q + 3]), z3 = cmul(csub(y[q + 1], y[q + 3]), c1);
-            buf[pad<P>(i0 + q * E)] = cadd(z0, z1);
-            buf[pad<P>(i0 + (q + 1) * E)] = cmul(csub(z0, z1), c3);
-            buf[pad<P>(i0 + (q + 2) * E)] = cadd(z2, z3);
-            buf[pad<P>(i0 + (q + 3) * E)] = cmul(csub(z2, z3), c3);
+            st(i0 + q * E, cadd(z0, z1));
+            st(i0 + (q + 1) * E, cmul(csub(z0, z1), c3));
+            st(i0 + (q + 2) * E, cadd(z2, z3));
+            st(i0 + (q + 3) * E, cmul(csub(z2, z3), c3));
         }
     }
 }
 
 // DIF pass over stages S, S/2 (Q = S/2): elements i0 + {0, Q, 2Q, 3Q},
 // i0 = (t / Q) 2S + t mod Q.
-template <bool P>
-__device__ __forceinline__ void dif4(float2* buf, const float2* tw, int L, int S)
+template <class LD, class ST>
+__device__ __forceinline__ void dif4(const float2* tw, int L, int S, LD ld, ST st)
 {
     const int Q = S >> 1, ts = L / (2 * S);
     for (int t = threadIdx.x; t < (L >> 2); t += blockDim.x) {
         const int j = t & (Q - 1);
         const int i0 = ((t - j) << 2) + j;
-        const float2 x0 = buf[pad<P>(i0)], x1 = buf[pad<P>(i0 + Q)], x2 = buf[pad<P>(i0 + S)], x3 = buf[pad<P>(i0 + S + Q)];
+        const float2 x0 = ld(i0), x1 = ld(i0 + Q), x2 = ld(i0 + S), x3 = ld(i0 + S + Q);
         const float2 y0 = cadd(x0, x2), y2 = cmul(csub(x0, x2), tw[j * ts]);
         const float2 y1 = cadd(x1, x3), y3 = cmul(csub(x1, x3), tw[(j + Q) * ts]);
         const float2 c = tw[j * 2 * ts];
-        buf[pad<P>(i0)] = cadd(y0, y1);
-        buf[pad<P>(i0 + Q)] = cmul(csub(y0, y1), c);
-        buf[pad<P>(i0 + S)] = cadd(y2, y3);
-        buf[pad<P>(i0 + S + Q)] = cmul(csub(y2, y3), c);
+        st(i0, cadd(y0, y1));
+        st(i0 + Q, cmul(csub(y0, y1), c));
+        st(i0 + S, cadd(y2, y3));
+        st(i0 + S + Q, cmul(csub(y2, y3), c));
+    }
+}
+
+// DIF stage of span 1 (twiddle tw[0]).
+template <class LD, class ST>
+__device__ __forceinline__ void dif2(const float2* tw, int L, LD ld, ST st)
+{
+    for (int t = threadIdx.x; t < (L >> 1); t += blockDim.x) {
+        const float2 u = ld(2 * t), w = ld(2 * t + 1);
+        st(2 * t, cadd(u, w));
+        st(2 * t + 1, cmul(csub(u, w), tw[0]));
     }
 }
 
 // DIT pass over stages S, 2S, 4S: elements i0 + k S, k < 8,
 // i0 = (t / S) 8S + t mod S.
-template <bool P>
-__device__ __forceinline__ void dit8(float2* buf, const float2* tw, int L, int S)
+template <class LD, class ST>
+__device__ __forceinline__ void dit8(const float2* tw, int L, int S, LD ld, ST st)
 {
     const int ts1 = L / (2 * S);
     for (int t = threadIdx.x; t < (L >> 3); t += blockDim.x) {
@@ -310,7 +327,7 @@ __device__ __forceinline__ void dit8(float2* buf, const float2* tw, int L, int S
         const int i0 = ((t - j) << 3) + j;
         float2 x[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = buf[pad<P>(i0 + k * S)];
+        for (int k = 0; k < 8; ++k) x[k] = ld(i0 + k * S);
         const float2 c1 = conj2(tw[j * ts1]);
         float2 y[8];
 #pragma unroll
@@ -332,108 +349,139 @@ __device__ __forceinline__ void dit8(float2* buf, const float2* tw, int L, int S
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float2 w = cmul(z[k + 4], conj2(tw[(j + k * S) * (ts1 >> 2)]));
-            buf[pad<P>(i0 + k * S)] = cadd(z[k], w);
-            buf[pad<P>(i0 + (k + 4) * S)] = csub(z[k], w);
+            st(i0 + k * S, cadd(z[k], w));
+            st(i0 + (k + 4) * S, csub(z[k], w));
         }
     }
 }
 
 // DIT pass over stages S, 2S: elements i0 + {0, S, 2S, 3S}, i0 = (t / S) 4S + t mod S.
-template <bool P>
-__device__ __forceinline__ void dit4(float2* buf, const float2* tw, int L, int S)
+template <class LD, class ST>
+__device__ __forceinline__ void dit4(const float2* tw, int L, int S, LD ld, ST st)
 {
     const int ts1 = L / (2 * S), ts2 = ts1 >> 1;
     for (int t = threadIdx.x; t < (L >> 2); t += blockDim.x) {
         const int j = t & (S - 1);
         const int i0 = ((t - j) << 2) + j;
         const float2 c1 = conj2(tw[j * ts1]), ca = conj2(tw[j * ts2]), cb = conj2(tw[(j + S) * ts2]);
-        const float2 x0 = buf[pad<P>(i0)], x1 = buf[pad<P>(i0 + S)], x2 = buf[pad<P>(i0 + 2 * S)], x3 = buf[pad<P>(i0 + 3 * S)];
+        const float2 x0 = ld(i0), x1 = ld(i0 + S), x2 = ld(i0 + 2 * S), x3 = ld(i0 + 3 * S);
         const float2 w1 = cmul(x1, c1), w3 = cmul(x3, c1);
         const float2 y0 = cadd(x0, w1), y1 = csub(x0, w1), y2 = cadd(x2, w3), y3 = csub(x2, w3);
         const float2 wa = cmul(y2, ca), wb = cmul(y3, cb);
-        buf[pad<P>(i0)] = cadd(y0, wa);
-        buf[pad<P>(i0 + 2 * S)] = csub(y0, wa);
-        buf[pad<P>(i0 + S)] = cadd(y1, wb);
-        buf[pad<P>(i0 + 3 * S)] = csub(y1, wb);
+        st(i0, cadd(y0, wa));
+        st(i0 + 2 * S, csub(y0, wa));
+        st(i0 + S, cadd(y1, wb));
+        st(i0 + 3 * S, csub(y1, wb));
     }
 }
 
-// The twiddle table is copied to LDS when it fits (TWL).
+// DIT stage of span 1 (twiddle conj(tw[0])).
+template <class LD, class ST>
+__device__ __forceinline__ void dit2(const float2* tw, int L, LD ld, ST st)
+{
+    for (int t = threadIdx.x; t < (L >> 1); t += blockDim.x) {
+        const float2 w = cmul(ld(2 * t + 1), conj2(tw[0]));
+        const float2 u = ld(2 * t);
+        st(2 * t, cadd(u, w));
+        st(2 * t + 1, csub(u, w));
+    }
+}
+
+// Workgroups are persistent over row pairs: each copies the twiddle table
+// to LDS once (when it fits, TWL) and then filters row pairs
+// blockIdx.x, blockIdx.x + gridDim.x, ...
 template <bool TWL, bool P = TWL>
 __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out, const float* __restrict__ H,
                                                     const float2* __restrict__ twg, int64_t nrows, FilterArgs fa)
 {
     extern __shared__ float2 buf[];
-    const int L = fa.L, L2 = L >> 1;
+    const int L = fa.L, L2 = L >> 1, logL = fa.logL;
     float2* const tws = buf + L + (P ? L >> 4 : 0);
     const float2* const tw = TWL ? tws : twg;
-    const int64_t r0 = 2 * (int64_t)blockIdx.x, r1 = r0 + 1;
-    const bool has1 = r1 < nrows;
-    const int iv0 = (int)(r0 % fa.nv), iv1 = (int)(r1 % fa.nv);
-    const float* a = in + r0 * fa.nu;
-    const float* bb = in + r1 * fa.nu;
-    for (int n = threadIdx.x; n < L; n += blockDim.x) {
-        float x = 0.0f, y = 0.0f;
-        if (n < fa.nu) {
-            x = a[n] * row_weight(fa, n, iv0);
-            if (has1) y = bb[n] * row_weight(fa, n, iv1);
-        }
-        buf[pad<P>(n)] = make_float2(x, y);
-    }
     if (TWL)
         for (int n = threadIdx.x; n < L2; n += blockDim.x) tws[n] = twg[n];
-    __syncthreads();
-    // forward DIF from span L/2: radix-8 passes, then the one or two stages left
-    int span = L2, rem = fa.logL;
-    for (; rem >= 3; rem -= 3, span >>= 3) {
-        dif8<P>(buf, tw, L, span);
-        __syncthreads();
-    }
-    if (rem == 2) {
-        dif4<P>(buf, tw, L, span);
-        __syncthreads();
-    } else if (rem == 1) {   // span 1, twiddle tw[0]
-        for (int t = threadIdx.x; t < L2; t += blockDim.x) {
-            const float2 u = buf[pad<P>(2 * t)], w = buf[pad<P>(2 * t + 1)];
-            buf[pad<P>(2 * t)] = cadd(u, w);
-            buf[pad<P>(2 * t + 1)] = cmul(csub(u, w), tw[0]);
+    auto lds_ld = [&](int i) { return buf[pad<P>(i)]; };
+    auto lds_st = [&](int i, float2 v) { buf[pad<P>(i)] = v; };
+    // the response (bit-reversed order, 1/L and tau folded in) times the
+    // angular scale, applied as the last forward pass stores
+    auto resp_st = [&](int i, float2 v) {
+        const float h = H[i] * fa.scale;
+        buf[pad<P>(i)] = make_float2(v.x * h, v.y * h);
+    };
+    const int64_t npairs = (nrows + 1) / 2;
+    for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+        const int64_t r0 = 2 * pr, r1 = r0 + 1;
+        const bool has1 = r1 < nrows;
+        const int iv0 = (int)(r0 % fa.nv), iv1 = (int)(r1 % fa.nv);
+        const float* a = in + r0 * fa.nu;
+        const float* bb = in + r1 * fa.nu;
+        float* oa = out + r0 * fa.nu;
+        float* ob = out + r1 * fa.nu;
+        // weighted rows, zero beyond nu (the linear convolution's padding)
+        auto src = [&](int n) {
+            float x = 0.0f, y = 0.0f;
+            if (n < fa.nu) {
+                x = a[n] * row_weight(fa, n, iv0);
+                if (has1) y = bb[n] * row_weight(fa, n, iv1);
+            }
+            return make_float2(x, y);
+        };
+        auto dst = [&](int n, float2 v) {
+            if (n < fa.nu) {
+                oa[n] = v.x;
+                if (has1) ob[n] = v.y;
+            }
+        };
+        __syncthreads();   // the previous pair is done with buf (and the twiddles are in)
+        if (logL >= 3) {
+            // forward DIF from span L/2: radix-8 passes, then the one or two
+            // stages left; the first reads the rows, the last applies the response
+            int span = L2, rem = logL;
+            if (rem == 3) dif8(tw, L, span, src, resp_st);
+            else dif8(tw, L, span, src, lds_st);
+            __syncthreads();
+            for (rem -= 3, span >>= 3; rem >= 3; rem -= 3, span >>= 3) {
+                if (rem == 3) dif8(tw, L, span, lds_ld, resp_st);
+                else dif8(tw, L, span, lds_ld, lds_st);
+                __syncthreads();
+            }
+            if (rem == 2) {
+                dif4(tw, L, span, lds_ld, resp_st);
+                __syncthreads();
+            } else if (rem == 1) {
+                dif2(tw, L, lds_ld, resp_st);
+                __syncthreads();
+            }
+            // inverse DIT from span 1: the one or two stages left over first,
+            // then radix-8 passes; the last (span L/8) writes the rows out
+            span = 1;
+            rem = logL % 3;
+            if (rem == 1) {
+                dit2(tw, L, lds_ld, lds_st);
+                __syncthreads();
+                span = 2;
+            } else if (rem == 2) {
+                dit4(tw, L, 1, lds_ld, lds_st);
+                __syncthreads();
+                span = 4;
+            }
+            for (; span < (L >> 3); span <<= 3) {
+                dit8(tw, L, span, lds_ld, lds_st);
+                __syncthreads();
+            }
+            dit8(tw, L, span, lds_ld, dst);
+        } else {
+            // L = 2 or 4: one load pass, the stages, the response, the store
+            for (int n = threadIdx.x; n < L; n += blockDim.x) lds_st(n, src(n));
+            __syncthreads();
+            if (logL == 2) dif4(tw, L, L2, lds_ld, resp_st);
+            else dif2(tw, L, lds_ld, resp_st);
+            __syncthreads();
+            if (logL == 2) dit4(tw, L, 1, lds_ld, lds_st);
+            else dit2(tw, L, lds_ld, lds_st);
+            __syncthreads();
+            for (int n = threadIdx.x; n < L; n += blockDim.x) dst(n, lds_ld(n));
         }
-        __syncthreads();
-    }
-    // response (bit-reversed order, 1/L and tau folded in) times the angular scale
-    for (int n = threadIdx.x; n < L; n += blockDim.x) {
-        const float h = H[n] * fa.scale;
-        const float2 z = buf[pad<P>(n)];
-        buf[pad<P>(n)] = make_float2(z.x * h, z.y * h);
-    }
-    __syncthreads();
-    // inverse DIT from span 1: the one or two stages left over first, then
-    // radix-8 passes
-    span = 1;
-    rem = fa.logL % 3;
-    if (rem == 1) {
-        for (int t = threadIdx.x; t < L2; t += blockDim.x) {
-            const float2 w = cmul(buf[pad<P>(2 * t + 1)], conj2(tw[0]));
-            const float2 u = buf[pad<P>(2 * t)];
-            buf[pad<P>(2 * t)] = cadd(u, w);
-            buf[pad<P>(2 * t + 1)] = csub(u, w);
-        }
-        __syncthreads();
-        span = 2;
-    } else if (rem == 2) {
-        dit4<P>(buf, tw, L, 1);
-        __syncthreads();
-        span = 4;
-    }
-    for (; span < L; span <<= 3) {
-        dit8<P>(buf, tw, L, span);
-        __syncthreads();
-    }
-    float* oa = out + r0 * fa.nu;
-    float* ob = out + r1 * fa.nu;
-    for (int n = threadIdx.x; n < fa.nu; n += blockDim.x) {
-        oa[n] = buf[pad<P>(n)].x;
-        if (has1) ob[n] = buf[pad<P>(n)].y;
     }
 }
 
@@ -472,7 +520,8 @@ hipError_t launch_fdk_filter(const Plan& p, int wang, const float* proj, float* 
     fa.wang_D = (float)(0.5 * (double)p.det.nu * g.dDetector[1] - (g.offDetector[1] < 0 ? -g.offDetector[1] : g.offDetector[1]));
     fa.wang_sign = g.offDetector[1] < 0 ? -1.0f : 1.0f;
     const int64_t nrows = nviews * p.det.nv;
-    const unsigned blocks = (unsigned)((nrows + 1) / 2);
+    // persistent workgroups: enough for 8 per CU, each looping over row pairs
+    const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 1) / 2, 2048);
     // up to L = 4096 the padded row and the twiddle table in LDS (51 KB)
     const size_t row = (size_t)p.fft_len + (size_t)(p.fft_len >> 4);   // padded row
     if (p.fft_len <= 4096) {

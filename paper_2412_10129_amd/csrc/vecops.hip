@@ -35,15 +35,49 @@ __global__ void __launch_bounds__(RB) k_final_sum(const double* __restrict__ par
     }
 }
 
+// Partial FP64 dot products, one per block (a fixed blocking: the result
+// depends only on n).  With V4 (both arrays 16-byte aligned) each lane
+// takes float4 pairs, two per step so that four loads are in flight; block
+// 0 adds the n mod 4 tail.  Products of two floats are exact in FP64.
+template <bool V4>
 __global__ void __launch_bounds__(RB) k_dot_partial(const float* __restrict__ a, const float* __restrict__ b,
                                                     int64_t n, double* __restrict__ part)
 {
     __shared__ double sh[RB];
-    double s = 0.0;
+    double s = 0.0, t = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RB;
-    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride)
-        s += (double)a[i] * (double)b[i];
-    s = block_sum(s, sh);
+    if (V4) {
+        const float4* __restrict__ a4 = reinterpret_cast<const float4*>(a);
+        const float4* __restrict__ b4 = reinterpret_cast<const float4*>(b);
+        const int64_t n4 = n >> 2;
+        int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+        for (; i + stride < n4; i += 2 * stride) {
+            const float4 x0 = a4[i], y0 = b4[i], x1 = a4[i + stride], y1 = b4[i + stride];
+            s = __builtin_fma((double)x0.x, (double)y0.x, s);
+            t = __builtin_fma((double)x1.x, (double)y1.x, t);
+            s = __builtin_fma((double)x0.y, (double)y0.y, s);
+            t = __builtin_fma((double)x1.y, (double)y1.y, t);
+            s = __builtin_fma((double)x0.z, (double)y0.z, s);
+            t = __builtin_fma((double)x1.z, (double)y1.z, t);
+            s = __builtin_fma((double)x0.w, (double)y0.w, s);
+            t = __builtin_fma((double)x1.w, (double)y1.w, t);
+        }
+        if (i < n4) {
+            const float4 x0 = a4[i], y0 = b4[i];
+            s = __builtin_fma((double)x0.x, (double)y0.x, s);
+            s = __builtin_fma((double)x0.y, (double)y0.y, s);
+            s = __builtin_fma((double)x0.z, (double)y0.z, s);
+            s = __builtin_fma((double)x0.w, (double)y0.w, s);
+        }
+        if (blockIdx.x == 0 && (int64_t)threadIdx.x < (n & 3)) {
+            const int64_t k = 4 * n4 + threadIdx.x;
+            t = __builtin_fma((double)a[k], (double)b[k], t);
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride)
+            s += (double)a[i] * (double)b[i];
+    }
+    s = block_sum(s + t, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -70,19 +104,69 @@ __global__ void __launch_bounds__(256) k_cgls_x(float* __restrict__ x, const flo
         x[i] = __builtin_fmaf(alpha, p[i], x[i]);
 }
 
+// r -= alpha q with |r|^2 (FP64) per block; V4 as in k_dot_partial.
+template <bool V4>
 __global__ void __launch_bounds__(RB) k_cgls_r(float* __restrict__ r, const float* __restrict__ q, int64_t n,
                                                const double* gamma, const double* delta, double* __restrict__ part)
 {
     __shared__ double sh[RB];
     const float alpha = safe_ratio(gamma, delta);
-    double s = 0.0;
+    double s = 0.0, t = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RB;
-    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
-        const float v = __builtin_fmaf(-alpha, q[i], r[i]);
-        r[i] = v;
-        s += (double)v * (double)v;
+    if (V4) {
+        float4* __restrict__ r4 = reinterpret_cast<float4*>(r);
+        const float4* __restrict__ q4 = reinterpret_cast<const float4*>(q);
+        const int64_t n4 = n >> 2;
+        int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+        for (; i + stride < n4; i += 2 * stride) {
+            float4 x0 = r4[i], x1 = r4[i + stride];
+            const float4 y0 = q4[i], y1 = q4[i + stride];
+            x0.x = __builtin_fmaf(-alpha, y0.x, x0.x);
+            x0.y = __builtin_fmaf(-alpha, y0.y, x0.y);
+            x0.z = __builtin_fmaf(-alpha, y0.z, x0.z);
+            x0.w = __builtin_fmaf(-alpha, y0.w, x0.w);
+            x1.x = __builtin_fmaf(-alpha, y1.x, x1.x);
+            x1.y = __builtin_fmaf(-alpha, y1.y, x1.y);
+            x1.z = __builtin_fmaf(-alpha, y1.z, x1.z);
+            x1.w = __builtin_fmaf(-alpha, y1.w, x1.w);
+            r4[i] = x0;
+            r4[i + stride] = x1;
+            s = __builtin_fma((double)x0.x, (double)x0.x, s);
+            t = __builtin_fma((double)x1.x, (double)x1.x, t);
+            s = __builtin_fma((double)x0.y, (double)x0.y, s);
+            t = __builtin_fma((double)x1.y, (double)x1.y, t);
+            s = __builtin_fma((double)x0.z, (double)x0.z, s);
+            t = __builtin_fma((double)x1.z, (double)x1.z, t);
+            s = __builtin_fma((double)x0.w, (double)x0.w, s);
+            t = __builtin_fma((double)x1.w, (double)x1.w, t);
+        }
+        if (i < n4) {
+            float4 x0 = r4[i];
+            const float4 y0 = q4[i];
+            x0.x = __builtin_fmaf(-alpha, y0.x, x0.x);
+            x0.y = __builtin_fmaf(-alpha, y0.y, x0.y);
+            x0.z = __builtin_fmaf(-alpha, y0.z, x0.z);
+            x0.w = __builtin_fmaf(-alpha, y0.w, x0.w);
+            r4[i] = x0;
+            s = __builtin_fma((double)x0.x, (double)x0.x, s);
+            s = __builtin_fma((double)x0.y, (double)x0.y, s);
+            s = __builtin_fma((double)x0.z, (double)x0.z, s);
+            s = __builtin_fma((double)x0.w, (double)x0.w, s);
+        }
+        if (blockIdx.x == 0 && (int64_t)threadIdx.x < (n & 3)) {
+            const int64_t k = 4 * n4 + threadIdx.x;
+            const float v = __builtin_fmaf(-alpha, q[k], r[k]);
+            r[k] = v;
+            t = __builtin_fma((double)v, (double)v, t);
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
+            const float v = __builtin_fmaf(-alpha, q[i], r[i]);
+            r[i] = v;
+            s += (double)v * (double)v;
+        }
     }
-    s = block_sum(s, sh);
+    s = block_sum(s + t, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -321,6 +405,8 @@ unsigned stream_blocks(int64_t n)
 
 }  // namespace
 
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 int reduce_blocks(int64_t n)
 {
     int64_t b = (n + RB * 16 - 1) / (RB * 16);
@@ -332,7 +418,10 @@ int reduce_blocks(int64_t n)
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* out, double* ws, hipStream_t s)
 {
     const int g = reduce_blocks(n);
-    hipLaunchKernelGGL(k_dot_partial, dim3(g), dim3(RB), 0, s, a, b, n, ws);
+    if (aligned16(a) && aligned16(b))
+        hipLaunchKernelGGL(k_dot_partial<true>, dim3(g), dim3(RB), 0, s, a, b, n, ws);
+    else
+        hipLaunchKernelGGL(k_dot_partial<false>, dim3(g), dim3(RB), 0, s, a, b, n, ws);
     hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(RB), 0, s, ws, g, 1, out);
     return hipGetLastError();
 }
@@ -348,7 +437,10 @@ hipError_t launch_cgls_xr(float* x, const float* p, int64_t nvol, float* r, cons
 {
     hipLaunchKernelGGL(k_cgls_x, dim3(stream_blocks(nvol)), dim3(256), 0, s, x, p, nvol, gamma, delta);
     const int g = reduce_blocks(nproj);
-    hipLaunchKernelGGL(k_cgls_r, dim3(g), dim3(RB), 0, s, r, q, nproj, gamma, delta, ws);
+    if (aligned16(r) && aligned16(q))
+        hipLaunchKernelGGL(k_cgls_r<true>, dim3(g), dim3(RB), 0, s, r, q, nproj, gamma, delta, ws);
+    else
+        hipLaunchKernelGGL(k_cgls_r<false>, dim3(g), dim3(RB), 0, s, r, q, nproj, gamma, delta, ws);
     hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(RB), 0, s, ws, g, 1, rnorm2);
     return hipGetLastError();
 }

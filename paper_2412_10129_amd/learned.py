@@ -15,8 +15,18 @@ the full circle, noiseless data from the same projector that reconstructs):
   from GPU events: time to reach 40 dB, and time to reach plain CGLS's best
   PSNR.
 
+Pairs are numbered: with the input iterations ks (KS by default, KS8 for
+the full training set), pair p comes from phantom seed p // len(ks) with
+the input after k = ks[p % len(ks)] iterations, so phantoms 0..249 give
+pairs 0..1999 with KS8.
+Training can run in segments: each `train` call makes the pairs of its own
+phantom range, trains on them, and saves the network with its Adam state;
+the next call resumes from that checkpoint with the next range (the pairs
+stream through the training once, a segment at a time).
+
 Command line (writes JSON / checkpoints where told):
     python -m paper_2412_10129_amd.learned train --phantoms 32 --steps 1500 --out ckpt.pt
+    python -m paper_2412_10129_amd.learned train --first-seed 32 --phantoms 32 --resume ckpt.pt --out ckpt2.pt
     python -m paper_2412_10129_amd.learned evaluate --ckpt ckpt.pt --phantoms 4 --iters 60
     python -m paper_2412_10129_amd.learned bench
 """
@@ -41,6 +51,7 @@ from .ops import Plan
 from .unet import UNet
 
 KS = (5, 10, 15, 20)
+KS8 = (3, 5, 8, 10, 13, 15, 18, 20)
 
 
 def _phantom(args):
@@ -51,11 +62,21 @@ def _phantom(args):
 
 def phantoms(name: str, seeds: Sequence[int], workers: int = 8) -> List[np.ndarray]:
     """Host phantoms (FP64 voxelisation, FP32 result) in a process pool."""
+    return list(phantom_stream(name, seeds, workers))
+
+
+def phantom_stream(name: str, seeds: Sequence[int], workers: int = 8):
+    """The same phantoms, yielded in seed order as the pool finishes them,
+    so the GPU can work on the first ones while the host makes the rest."""
     workers = max(1, min(workers, len(seeds)))
     if workers == 1:
-        return [_phantom((name, s)) for s in seeds]
+        for s in seeds:
+            yield _phantom((name, s))
+        return
     with ProcessPoolExecutor(workers) as ex:
-        return list(ex.map(_phantom, [(name, s) for s in seeds]))
+        futs = [ex.submit(_phantom, (name, s)) for s in seeds]
+        for f in futs:
+            yield f.result()
 
 
 def data_range(geo, x_gt: np.ndarray) -> float:
@@ -69,9 +90,10 @@ def data_range(geo, x_gt: np.ndarray) -> float:
     return float(vals.max() - vals.min())
 
 
-def make_pairs(plan: Plan, dense: Plan, vols: List[np.ndarray], kind: str = "interp", ks=KS, dense_iters: int = 20):
+def make_pairs(plan: Plan, dense: Plan, vols, kind: str = "interp", ks=KS, dense_iters: int = 20):
     """(inputs, targets) on the device: sparse-view CGLS-k iterates and the
-    dense-view CGLS reconstruction of the same phantom."""
+    dense-view CGLS reconstruction of the same phantom (`vols` may be any
+    iterable of host phantoms)."""
     inputs, targets = [], []
     for v in vols:
         xg = torch.from_numpy(v).to(plan.device)
@@ -115,10 +137,15 @@ def _first_at(psnr, ms, level):
     return (float(t[idx[0]]) if len(idx) else None), (int(idx[0]) + 1 if len(idx) else None)
 
 
-def evaluate(plan: Plan, net: UNet, vols: List[np.ndarray], niter: int = 60, every: int = 5, ratio: float = 1.05,
-             kind: str = "interp", target_db: float = 40.0, log=print) -> Dict:
+def evaluate(plan: Plan, net: UNet, vols, niter: int = 60, every: int = 5, ratio: float = 1.05,
+             kind: str = "interp", target_db: float = 40.0, log=print, on_run=None) -> Dict:
     """Plain CGLS vs PnP-CGLS on each volume: PSNR histories, solver times,
-    time to `target_db`, and time for PnP to reach plain CGLS's best."""
+    time to `target_db`, and time for PnP to reach plain CGLS's best.
+
+    With `on_run`, every iterate of both runs is kept on the device and
+    on_run(n, x_gt_host, res, iterates) is called per volume with
+    iterates = {"cgls": [...], "pnp": [...]} (device tensors, freed after
+    the call), e.g. to judge them independently."""
     runs = []
     geo = plan.geo
     for n, v in enumerate(vols):
@@ -126,11 +153,13 @@ def evaluate(plan: Plan, net: UNet, vols: List[np.ndarray], niter: int = 60, eve
         R = data_range(geo, v)
         b = plan.forward(xg, kind=kind)
         res = {}
+        its = {}
         for name, ev in (("cgls", niter + 1), ("pnp", every)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            its[name] = [] if on_run is not None else None
             _, h = algs.pnp_cgls(plan, b, niter, net, every=ev, ratio=ratio, kind=kind, x_gt=xg, data_range=R,
-                                 timing=True)
+                                 timing=True, keep=its[name])
             wall = time.perf_counter() - t0
             res[name] = {"psnr": [float(p) for p in h["psnr"]], "ms": [float(m) for m in h["ms"]],
                          "accepted": h["accepted"], "ratios": h["ratios"], "wall_s": wall}
@@ -144,35 +173,64 @@ def evaluate(plan: Plan, net: UNet, vols: List[np.ndarray], niter: int = 60, eve
         log(f"volume {n}: cgls best {best:.2f} dB, pnp best {res['pnp']['best_psnr']:.2f} dB; "
             f"to {target_db} dB: cgls {res['cgls']['ms_to_target']} ms, pnp {res['pnp']['ms_to_target']} ms; "
             f"pnp to cgls best {res['pnp']['ms_to_cgls_best']} ms vs {res['cgls']['ms_to_cgls_best']} ms")
+        if on_run is not None:
+            on_run(n, v, res, its)
+        del its
         runs.append(res)
     return {"runs": runs, "niter": niter, "every": every, "ratio": ratio, "kind": kind, "target_db": target_db}
 
 
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_sparse256.pt")
+
+
+def save_weights(net: UNet, path: str, meta: Dict) -> None:
+    """The trained network's FP32 parameters (no optimiser state) with a
+    description of its training."""
+    torch.save({"params": net.params.detach().cpu(), "meta": json.dumps(meta)}, path)
+
+
+def load_weights(net: UNet, path: str) -> Dict:
+    sd = torch.load(path, map_location="cpu", weights_only=True)
+    net.params.copy_(sd["params"].to(net.device))
+    net.pack()
+    return json.loads(sd["meta"])
+
+
 def quick_benchmark(train_phantoms: int = 4, steps: int = 600, test_phantoms: int = 2, niter: int = 60,
-                    kind: str = "interp", workers: int = 8, log=print) -> Dict:
-    """A bounded run of the whole learned-prior pipeline for the benchmark:
-    pairs from `train_phantoms` phantoms (seeds 0..), `steps` Adam steps,
-    then plain CGLS and PnP-CGLS on `test_phantoms` test volumes (seeds
-    10000..).  Returns per-volume times to 40 dB and to plain CGLS's best."""
+                    kind: str = "interp", workers: int = 8, log=print, weights: Optional[str] = None) -> Dict:
+    """A bounded run of the learned prior for the benchmark: with `weights`
+    (a saved trained network) plain CGLS and PnP-CGLS with that network on
+    `test_phantoms` test volumes (seeds 10000..); otherwise first a short
+    training run (pairs from `train_phantoms` phantoms, seeds 0.., `steps`
+    Adam steps).  Returns per-volume times to 40 dB and to plain CGLS's
+    best."""
     t0 = time.perf_counter()
     geo, ang = synth.workload("sparse256")
     plan = Plan(geo, ang)
-    dense = Plan(geo, synth.circular_angles(720))
-    vols = phantoms("sparse256", range(train_phantoms), workers)
-    inputs, targets = make_pairs(plan, dense, vols, kind)
-    del dense
     net = UNet(seed=0)
-    train(net, inputs, targets, steps, log=lambda m: None)
-    del inputs, targets
+    trained = None
+    if weights and os.path.exists(weights):
+        trained = load_weights(net, weights)
+    else:
+        dense = Plan(geo, synth.circular_angles(720))
+        vols = phantoms("sparse256", range(train_phantoms), workers)
+        inputs, targets = make_pairs(plan, dense, vols, kind)
+        del dense
+        train(net, inputs, targets, steps, log=lambda m: None)
+        del inputs, targets
     test = phantoms("sparse256", range(10000, 10000 + test_phantoms), workers)
     res = evaluate(plan, net, test, niter, kind=kind, log=log)
     rr = res["runs"]
     out = {
         "metric": "time to 40 dB PSNR, PnP-CGLS (learned prior) vs plain CGLS",
         "unit": "ms",
-        "config": {"workload": "sparse256", "volume": list(geo.nVoxel), "views": len(ang), "projector": kind,
-                   "train_phantoms": train_phantoms, "train_pairs": 4 * train_phantoms, "train_steps": steps,
-                   "test_phantoms": test_phantoms, "iterations": niter, "denoise_every": 5},
+        "config": ({"workload": "sparse256", "volume": list(geo.nVoxel), "views": len(ang), "projector": kind,
+                    "network": "saved weights", "training": trained, "test_phantoms": test_phantoms,
+                    "iterations": niter, "denoise_every": 5} if trained is not None else
+                   {"workload": "sparse256", "volume": list(geo.nVoxel), "views": len(ang), "projector": kind,
+                    "network": "trained in the run (reduced)", "train_phantoms": train_phantoms,
+                    "train_pairs": len(KS) * train_phantoms, "train_steps": steps, "test_phantoms": test_phantoms,
+                    "iterations": niter, "denoise_every": 5}),
         "cgls_ms_to_40db": [r["cgls"]["ms_to_target"] for r in rr],
         "pnp_ms_to_40db": [r["pnp"]["ms_to_target"] for r in rr],
         "cgls_best_db": [round(r["cgls"]["best_psnr"], 3) for r in rr],
@@ -237,6 +295,9 @@ def main(argv=None):
     t.add_argument("--kind", default="interp")
     t.add_argument("--out", required=True)
     t.add_argument("--workers", type=int, default=8)
+    t.add_argument("--resume", default=None, help="checkpoint (network and Adam state) to continue from")
+    t.add_argument("--seed", type=int, default=0, help="crop sampling seed of this segment")
+    t.add_argument("--ks", default=",".join(map(str, KS)), help="CGLS iterations of the inputs, e.g. 3,5,8,10,13,15,18,20")
     e = sub.add_parser("evaluate")
     e.add_argument("--ckpt", required=True)
     e.add_argument("--phantoms", type=int, default=4)
@@ -245,6 +306,11 @@ def main(argv=None):
     e.add_argument("--kind", default="interp")
     e.add_argument("--out", default=None)
     e.add_argument("--workers", type=int, default=8)
+    x = sub.add_parser("export", help="save a checkpoint's network parameters as the weights file")
+    x.add_argument("--ckpt", required=True)
+    x.add_argument("--out", default=WEIGHTS)
+    x.add_argument("--pairs", type=int, required=True)
+    x.add_argument("--ks", default=",".join(map(str, KS8)))
     b = sub.add_parser("bench", help="time the U-Net forward and one training step")
     b.add_argument("--repeat", type=int, default=3)
     a = ap.parse_args(argv)
@@ -252,29 +318,54 @@ def main(argv=None):
     if a.cmd == "bench":
         bench_unet(a.repeat, log)
         return
+    if a.cmd == "export":
+        net = UNet(seed=0)
+        sd = torch.load(a.ckpt, map_location="cpu", weights_only=True)
+        net.load_state_dict({k: (v.to(net.device) if k != "t" else v) for k, v in sd.items()
+                             if k in ("params", "m", "v", "t")})
+        seen = sorted(int(v) for v in sd.get("phantoms", torch.zeros(0, dtype=torch.int64)).tolist())
+        meta = {"pairs": a.pairs, "phantom_seeds": [seen[0], seen[-1]] if seen else None, "phantoms": len(seen),
+                "input_iterations": a.ks, "target": "CGLS-20 on 720 views", "adam_steps": int(net.t),
+                "crop": 64, "batch": 4}
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        save_weights(net, a.out, meta)
+        log(json.dumps(meta))
+        return
     geo, ang = synth.workload("sparse256")
     plan = Plan(geo, ang)
     if a.cmd == "train":
         t0 = time.perf_counter()
-        vols = phantoms("sparse256", range(a.first_seed, a.first_seed + a.phantoms), a.workers)
-        log(f"{len(vols)} phantoms in {time.perf_counter() - t0:.1f} s")
-        t0 = time.perf_counter()
+        seeds = range(a.first_seed, a.first_seed + a.phantoms)
         dense = Plan(geo, synth.circular_angles(720))
-        inputs, targets = make_pairs(plan, dense, vols, a.kind)
+        ks = tuple(int(k) for k in a.ks.split(","))
+        inputs, targets = make_pairs(plan, dense, phantom_stream("sparse256", seeds, a.workers), a.kind, ks=ks)
         del dense
         torch.cuda.synchronize()
-        log(f"{len(inputs)} pairs in {time.perf_counter() - t0:.1f} s")
+        nk = len(ks)
+        log(f"pairs {nk * a.first_seed}..{nk * (a.first_seed + a.phantoms) - 1} ({len(inputs)}, inputs after "
+            f"{a.ks} iterations) from phantoms {a.first_seed}..{a.first_seed + a.phantoms - 1} in "
+            f"{time.perf_counter() - t0:.1f} s")
         net = UNet(seed=0)
+        seen = []
+        if a.resume:
+            sd = torch.load(a.resume, map_location="cpu", weights_only=True)
+            net.load_state_dict({k: (v.to(net.device) if k != "t" else v) for k, v in sd.items()
+                                 if k in ("params", "m", "v", "t")})
+            seen = [int(v) for v in sd.get("phantoms", torch.zeros(0, dtype=torch.int64)).tolist()]
+            log(f"resumed at Adam step {net.t} ({len(seen)} phantoms seen)")
         t0 = time.perf_counter()
-        hist = train(net, inputs, targets, a.steps, a.crop, a.batch, log=log)
+        hist = train(net, inputs, targets, a.steps, a.crop, a.batch, seed=a.seed, log=log)
         torch.cuda.synchronize()
         log(f"trained {a.steps} steps in {time.perf_counter() - t0:.1f} s")
-        torch.save({k: (v.cpu() if isinstance(v, torch.Tensor) else v) for k, v in net.state_dict().items()}, a.out)
+        sd = {k: (v.cpu() if isinstance(v, torch.Tensor) else v) for k, v in net.state_dict().items()}
+        sd["phantoms"] = torch.tensor(seen + list(seeds), dtype=torch.int64)
+        torch.save(sd, a.out)
         log(json.dumps({"train_mse": hist}))
     else:
         net = UNet(seed=0)
         sd = torch.load(a.ckpt, map_location="cpu", weights_only=True)
-        net.load_state_dict({k: (v.to(net.device) if k != "t" else v) for k, v in sd.items()})
+        net.load_state_dict({k: (v.to(net.device) if k != "t" else v) for k, v in sd.items()
+                             if k in ("params", "m", "v", "t")})
         vols = phantoms("sparse256", range(a.first_seed, a.first_seed + a.phantoms), a.workers)
         res = evaluate(plan, net, vols, a.iters, kind=a.kind, log=log)
         summ = {

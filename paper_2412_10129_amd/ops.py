@@ -15,6 +15,8 @@ from . import _lib as L
 
 _PROJ = {"siddon": L.CTMI_SIDDON, "interp": L.CTMI_INTERP}
 _BP = {"siddon": L.CTMI_BP_SIDDON, "interp": L.CTMI_BP_INTERP, "fdk": L.CTMI_BP_FDK}
+_BP_OP = {"siddon": L.CTMI_OP_BACKPROJECT_SIDDON, "interp": L.CTMI_OP_BACKPROJECT_INTERP,
+          "fdk": L.CTMI_OP_BACKPROJECT_FDK}
 
 
 def _stream(stream=None):
@@ -82,6 +84,7 @@ class Plan:
                 L.check(L.lib().ctmi_plan_create_views(ctypes.byref(g), tab, self.nviews, ctypes.byref(h)))
         self._h = h
         self._ws = torch.empty(L.lib().ctmi_reduce_workspace_bytes(0) // 8, dtype=torch.float64, device=self.device)
+        self._ws_bytes = {}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -116,16 +119,35 @@ class Plan:
         L.check(L.lib().ctmi_forward(self._h, _PROJ[kind], pv, po, view0, nviews, _stream(stream)))
         return out
 
+    def workspace_size(self, op: int) -> int:
+        """Device workspace bytes of a libctmi operation (CTMI_OP_*) on this plan."""
+        n = ctypes.c_size_t()
+        L.check(L.lib().ctmi_workspace_size(self._h, int(op), ctypes.byref(n)))
+        return int(n.value)
+
     def backproject(self, proj: torch.Tensor, out: Optional[torch.Tensor] = None, kind: str = "siddon",
-                    beta: float = 0.0, view0: int = 0, nviews: Optional[int] = None, stream=None) -> torch.Tensor:
-        """out = beta * out + B proj; kind 'siddon'/'interp' = matched A^T, 'fdk' = FDK backprojector."""
+                    beta: float = 0.0, view0: int = 0, nviews: Optional[int] = None, stream=None,
+                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """out = beta * out + B proj; kind 'siddon'/'interp' = matched A^T, 'fdk' = FDK backprojector.
+        The workspace (interpolated A^T only) comes from torch's caching
+        allocator on the call's stream unless `ws` (a device tensor of at
+        least workspace_size bytes) is given."""
         view0, nviews = self._range(view0, nviews)
         if out is None:
             out = torch.empty(self.vol_shape, dtype=torch.float32, device=self.device)
             beta = 0.0
         pp = _ptr(proj, "proj", nviews * self.det_shape[0] * self.det_shape[1], self.device)
         po = _ptr(out, "vol", int(np.prod(self.vol_shape)), self.device)
-        L.check(L.lib().ctmi_backproject(self._h, _BP[kind], pp, po, view0, nviews, float(beta), _stream(stream)))
+        nbytes = self._ws_bytes.get(kind)
+        if nbytes is None:
+            nbytes = self._ws_bytes[kind] = self.workspace_size(_BP_OP[kind])
+        if nbytes and ws is None:
+            with torch.cuda.stream(stream) if stream is not None else _nullctx():
+                ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        wp = ctypes.c_void_p(ws.data_ptr()) if ws is not None else ctypes.c_void_p()
+        wb = ws.numel() * ws.element_size() if ws is not None else 0
+        L.check(L.lib().ctmi_backproject(self._h, _BP[kind], pp, po, view0, nviews, float(beta), wp, wb,
+                                         _stream(stream)))
         return out
 
     def fdk_filter(self, proj: torch.Tensor, out: Optional[torch.Tensor] = None, wang: bool = False, view0: int = 0,
@@ -138,6 +160,21 @@ class Plan:
                                         _ptr(out, "out", n, self.device), view0, nviews, _stream(stream)))
         return out
 
+    def flatten_curved(self, curved: torch.Tensor, cd, out: Optional[torch.Tensor] = None, view0: int = 0,
+                       nviews: Optional[int] = None, stream=None) -> torch.Tensor:
+        """Flattening transformation: projections on the curved detector `cd`
+        (nDetector, dDetector, radius, offDetector) resampled onto this
+        plan's flat detector."""
+        view0, nviews = self._range(view0, nviews)
+        if out is None:
+            out = torch.empty(self.proj_shape(nviews), dtype=torch.float32, device=self.device)
+        c = L.curved_struct(cd)
+        nc = nviews * int(cd.nDetector[0]) * int(cd.nDetector[1])
+        L.check(L.lib().ctmi_flatten_curved(self._h, ctypes.byref(c), _ptr(curved, "curved", nc, self.device),
+                                            _ptr(out, "flat", nviews * self.det_shape[0] * self.det_shape[1],
+                                                 self.device), view0, nviews, _stream(stream)))
+        return out
+
     # ---------------------------------------------------------- reductions
     def fov_sq_err(self, x: torch.Tensor, gt: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
         """out[0:2] (float64 device) = (sum of squared error, count) inside the FOV cylinder."""
@@ -146,6 +183,20 @@ class Plan:
                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self._ws.data_ptr()),
                                         self._ws.numel() * 8, _stream(stream)))
         return out
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+def stream_check(stream=None) -> None:
+    """Raise if the device reported an asynchronous error on `stream` (or an
+    earlier launch failed)."""
+    L.check(L.lib().ctmi_stream_check(_stream(stream)))
 
 
 def _ws(device):

@@ -1,0 +1,140 @@
+"""The C-ABI boundary on the GPU: caller-owned workspaces and their errors,
+immutable plans shared by concurrent streams, the stream check, and the
+adjoints' behaviour on non-finite and extreme-magnitude projections (the
+exact transpose of section 2.2.1's Krylov methods must stay linear at every
+scale and must not hide a NaN or an infinity in its input)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from synth import Geometry
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+RAGGED = Geometry(DSD=400.0, DSO=250.0, nVoxel=(40, 36, 44), dVoxel=(1.1, 1.0, 0.9), nDetector=(50, 70),
+                  dDetector=(1.3, 1.2), offOrigin=(0.7, -1.1, 0.4), offDetector=(0.9, -1.6))
+
+
+def _angles(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.uniform(0, 2 * np.pi, n))
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_10129_amd as P
+    return P
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_workspace_sizes_and_errors(P):
+    from paper_2412_10129_amd import _lib as L
+    plan = P.Plan(RAGGED, _angles(8, 1))
+    nb = -(-44 // 16) * -(-36 // 16) * -(-40 // 8)
+    assert plan.workspace_size(L.CTMI_OP_BACKPROJECT_INTERP) == nb * 553 * 4
+    for op in (L.CTMI_OP_FORWARD_SIDDON, L.CTMI_OP_FORWARD_INTERP, L.CTMI_OP_BACKPROJECT_SIDDON,
+               L.CTMI_OP_BACKPROJECT_FDK, L.CTMI_OP_FDK_FILTER):
+        assert plan.workspace_size(op) == 0
+    assert plan.workspace_size(L.CTMI_OP_FOV_SQ_ERR) == L.lib().ctmi_reduce_workspace_bytes(0)
+    n = ctypes.c_size_t()
+    assert L.lib().ctmi_workspace_size(plan._h, 99, ctypes.byref(n)) == L.CTMI_EINVAL
+    assert L.lib().ctmi_workspace_size(None, L.CTMI_OP_FORWARD_SIDDON, ctypes.byref(n)) == L.CTMI_EINVAL
+    y = _dev(synth.uniform_projections(RAGGED, 8, 2))
+    vol = torch.zeros(plan.vol_shape, device="cuda")
+    need = plan.workspace_size(L.CTMI_OP_BACKPROJECT_INTERP)
+    ws = torch.empty(need + 64, dtype=torch.uint8, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call(wp, wb, bp=L.CTMI_BP_INTERP):
+        return L.lib().ctmi_backproject(plan._h, bp, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(vol.data_ptr()),
+                                        0, 8, 0.0, wp, wb, s)
+    assert call(None, 0) == L.CTMI_EWORKSPACE
+    assert call(ctypes.c_void_p(ws.data_ptr()), need - 4) == L.CTMI_EWORKSPACE
+    assert call(ctypes.c_void_p(ws.data_ptr() + 4), need) == L.CTMI_EINVAL
+    assert call(ctypes.c_void_p(ws.data_ptr()), need) == L.CTMI_OK
+    assert call(None, 0, L.CTMI_BP_SIDDON) == L.CTMI_OK     # the Siddon adjoint needs none
+    torch.cuda.synchronize()
+    P.stream_check()
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_one_plan_on_concurrent_streams(P, kind):
+    """Plans are immutable: adjoints of different data on two streams at
+    once, each with its own workspace, equal the serial results bit for bit."""
+    geo, ang = RAGGED, _angles(16, 3)
+    plan = P.Plan(geo, ang)
+    ys = [_dev(synth.uniform_projections(geo, len(ang), 10 + i)) for i in range(2)]
+    serial = [_host(plan.backproject(y, kind=kind)) for y in ys]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty(plan.vol_shape, device="cuda") for _ in ys]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for s, y, o in zip(streams, ys, outs):
+            with torch.cuda.stream(s):
+                plan.backproject(y, out=o, kind=kind, stream=s)
+        for s in streams:
+            P.stream_check(s)
+        torch.cuda.synchronize()
+        for o, want in zip(outs, serial):
+            assert np.array_equal(o.cpu().numpy(), want), (kind, rep)
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_adjoint_is_linear_at_extreme_scales(P, kind):
+    """A^T(c y) = c A^T(y): exact for powers of two far outside the usual
+    range (the fixed-point scale follows the data's exponent), and to FP32
+    rounding for other factors."""
+    geo, ang = RAGGED, _angles(12, 4)
+    plan = P.Plan(geo, ang)
+    y = synth.uniform_projections(geo, len(ang), 5)
+    base = _host(plan.backproject(_dev(y), kind=kind)).astype(np.float64)
+    for k in (-90, -40, 40, 100):
+        got = _host(plan.backproject(_dev(y * np.float32(2.0 ** k)), kind=kind)).astype(np.float64)
+        assert np.array_equal(got, base * 2.0 ** k), (kind, k)
+    for c in (1e-32, 3e-20, 7e25):
+        got = _host(plan.backproject(_dev(y * np.float32(c)), kind=kind)).astype(np.float64)
+        assert _rel(got / c, base) < 1e-6, (kind, c)
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_nonfinite_projections_reach_the_output(P, orc, kind):
+    """NaN and +-Inf in y: the voxels the oracle's sum makes non-finite are
+    exactly those the GPU sets to NaN, and every other voxel matches the
+    oracle to the parity tolerance."""
+    geo, ang = RAGGED, _angles(10, 6)
+    y = synth.uniform_projections(geo, len(ang), 7).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(8))
+    bad = [(int(rng.integers(len(ang))), int(rng.integers(8, 42)), int(rng.integers(8, 62))) for _ in range(6)]
+    for i, (k, iv, iu) in enumerate(bad):
+        y[k, iv, iu] = (np.nan, np.inf, -np.inf)[i % 3]
+    plan = P.Plan(geo, ang)
+    got = _host(plan.backproject(_dev(y), kind=kind))
+    want = orc.backward(geo, ang, y, kind)
+    bad_o = ~np.isfinite(want)
+    assert bad_o.sum() > 50
+    assert np.array_equal(~np.isfinite(got), bad_o), (kind, int((~np.isfinite(got)).sum()), int(bad_o.sum()))
+    ok = ~bad_o
+    assert _rel(got[ok], want[ok]) < 1e-4
+    # the forward pass of finite data is untouched by the change
+    x = synth.uniform_volume(geo, 9)
+    assert _rel(_host(plan.forward(_dev(x), kind=kind)), orc.forward(geo, ang, x, kind)) < 1e-4

@@ -82,6 +82,40 @@ def test_512_backward_sampled_voxels_and_determinism(P, orc, cbct, kind):
     assert _rel(got, want) < 1e-4, _rel(got, want)
 
 
+def _brick_face_voxels(geo, n, seed):
+    """Voxels on the adjoint's brick faces, edges and corners (16 x 16 x 8
+    bricks: x or y = 0 or 15 mod 16, z = 0 or 7 mod 8), where its
+    neighbour-shell additions land, inside the FOV cylinder."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nz, ny, nx = geo.nVoxel
+    out = []
+    while len(out) < n:
+        bx, by, bz = int(rng.integers(nx // 16)), int(rng.integers(ny // 16)), int(rng.integers(nz // 8))
+        kind = int(rng.integers(7))            # 1..7: faces (1 axis), edges (2), corners (3); bit per axis
+        kind += 1
+        lx = (0 if rng.integers(2) else 15) if kind & 1 else int(rng.integers(1, 15))
+        ly = (0 if rng.integers(2) else 15) if kind & 2 else int(rng.integers(1, 15))
+        lz = (0 if rng.integers(2) else 7) if kind & 4 else int(rng.integers(1, 7))
+        iz, iy, ix = bz * 8 + lz, by * 16 + ly, bx * 16 + lx
+        if (iy + 0.5 - ny / 2) ** 2 + (ix + 0.5 - nx / 2) ** 2 < (0.9 * nx / 2) ** 2:
+            out.append((iz, iy, ix))
+    return [np.array(c) for c in zip(*out)]
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_512_backward_brick_faces_and_interior(P, orc, cbct, kind):
+    """A^T at 512 brick-face, edge and corner voxels and 256 random interior
+    ones (rel-L2 1e-4 over each set, and every voxel within 1e-3)."""
+    geo, ang = cbct["geo"], cbct["ang"]
+    out = cbct["plan"].backproject(cbct["y"], kind=kind)
+    for name, (iz, iy, ix) in (("faces", _brick_face_voxels(geo, 512, 81)), ("random", _fov_voxels(geo, 256, 82))):
+        got = out[torch.from_numpy(iz).cuda(), torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()]
+        got = got.double().cpu().numpy()
+        want = orc.adjoint_voxels(geo, ang, cbct["y64"], iz, iy, ix, kind)
+        assert _rel(got, want) < 1e-4, (name, _rel(got, want))
+        assert np.max(np.abs(got / want - 1.0)) < 1e-3, name
+
+
 def test_512_fdk_backprojector_sampled_voxels(P, orc, cbct):
     geo, ang = cbct["geo"], cbct["ang"]
     out = cbct["plan"].backproject(cbct["y"], kind="fdk")
@@ -123,6 +157,54 @@ def _box_chords(geo, ang, views, ivs, ius, orc):
         a1 = min(1.0, np.min(np.maximum(a_lo, a_hi)))
         out[n] = max(a1 - a0, 0.0) * np.linalg.norm(d)
     return out
+
+
+def test_1024_interp_forward_sampled_rays(P, orc, large):
+    """The interpolated projector at 1024^3 x 1440 (offsets past 2^31 in the
+    projections) on a U(0,1) volume, at 1024 rays against the oracle."""
+    geo, ang, plan = large["geo"], large["ang"], large["plan"]
+    xh = synth.uniform_volume(geo, 83)
+    out = plan.forward(torch.from_numpy(xh).cuda(), kind="interp")
+    rng = np.random.Generator(np.random.PCG64(84))
+    n = 1024
+    views = np.concatenate([rng.integers(0, len(ang), n - 64), np.full(64, len(ang) - 1)])
+    ivs = rng.integers(0, geo.nDetector[0], n)
+    ius = rng.integers(0, geo.nDetector[1], n)
+    got = out[torch.from_numpy(views).cuda(), torch.from_numpy(ivs).cuda(), torch.from_numpy(ius).cuda()]
+    got = got.double().cpu().numpy()
+    del out
+    want = orc.forward_rays(geo, ang, xh, views, ivs, ius, "interp")
+    assert _rel(got, want) < 1e-4, _rel(got, want)
+
+
+def test_1024_fdk_wang_central_slice_vs_oracle(P, orc, large):
+    """FDK with Wang weights at 1024^3 x 1440 on the offset detector, on the
+    GPU's full launch, against the oracle at central-slice voxels.  The
+    projections are the closed-form line integrals of the head phantom on
+    the 16 detector rows around the central row (zero elsewhere): the
+    filter works row by row and a central-slice voxel projects between the
+    two central rows in every view, so the oracle needs only those 16 rows
+    (a detector of 16 rows with the same centre)."""
+    geo, ang, plan = large["geo"], large["ang"], large["plan"]
+    nv, nu = geo.nDetector
+    band = geo.replace(nDetector=(16, nu))
+    ells = synth.head_phantom(geo, 3)
+    q = orc.analytic_projections(band, ang, ells)           # (1440, 16, nu) FP64
+    y = torch.zeros((len(ang), nv, nu), device="cuda")
+    y[:, nv // 2 - 8:nv // 2 + 8] = torch.from_numpy(q.astype(np.float32)).cuda()
+    rec = P.fdk(plan, y, wang=True)
+    del y
+    rng = np.random.Generator(np.random.PCG64(85))
+    r = rng.uniform(0, 0.85 * geo.nVoxel[2] / 2, 96)
+    t = rng.uniform(0, 2 * np.pi, 96)
+    ix = np.clip((geo.nVoxel[2] / 2 + r * np.cos(t)).astype(np.int64), 0, geo.nVoxel[2] - 1)
+    iy = np.clip((geo.nVoxel[1] / 2 + r * np.sin(t)).astype(np.int64), 0, geo.nVoxel[1] - 1)
+    iz = np.full(96, geo.nVoxel[0] // 2)
+    got = rec[torch.from_numpy(iz).cuda(), torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()]
+    got = got.double().cpu().numpy()
+    qf = orc.fdk_filter(band, q.astype(np.float32).astype(np.float64), ntotal=len(ang), wang=True)
+    want = orc.bfdk_voxels(band, ang, qf, iz, iy, ix)
+    assert _rel(got, want) < 1e-4, _rel(got, want)
 
 
 def test_1024_siddon_forward_constant_volume_is_box_chord(P, orc, large):
