@@ -113,6 +113,58 @@ def profile_summary(db_path, top=12):
     return "\n".join(lines)
 
 
+def _pmc_means(db_paths):
+    """Per-kernel mean of every PMC counter over the dispatches in the given
+    rocprofv3 databases (counters from several passes merged by kernel)."""
+    import collections
+    import re
+    import sqlite3
+    short = lambda n: re.sub(r"^void ", "", n.replace("ctmi::(anonymous namespace)::", "").split("(")[0]).strip()
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in db_paths:
+        con = sqlite3.connect(path)
+        rows = con.execute("select name, dispatch_id, counter_name, sum(counter_value) from pmc_events "
+                           "group by name, dispatch_id, counter_name").fetchall()
+        for name, _, cn, v in rows:
+            acc[short(name)][cn].append(v)
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+
+def profile_derived(db_paths, cus=256, xcds=8):
+    """Markdown table of derived per-kernel metrics from the counter passes
+    (FETCH_SIZE; WRITE_SIZE, TCC_HIT_sum, TCC_MISS_sum; SQ counters with
+    GRBM_GUI_ACTIVE): HBM bytes per dispatch scaled by the stream-copy
+    kernel of the same run (it moves 2^30 bytes each way), L2 hit rate,
+    VALU busy (rocprofv3's VALUBusy: SQ_ACTIVE_INST_VALU / CUs / cycles),
+    VALU utilisation (active lanes per VALU instruction), VALU
+    wave-instructions per CU-cycle, and LDS bank-conflict cycles per CU-cycle.
+    GRBM_GUI_ACTIVE is summed over the XCDs; the per-XCD cycles divide it by
+    their count."""
+    m = _pmc_means(db_paths)
+    cal = m.get("k_stream_copy", {})
+    ff = (1 << 20) / cal["FETCH_SIZE"] if cal.get("FETCH_SIZE") else None
+    wf = (1 << 20) / cal["WRITE_SIZE"] if cal.get("WRITE_SIZE") else None
+    lines = [f"calibration: the 1 GiB stream copy reads FETCH_SIZE {cal.get('FETCH_SIZE', 0):.6g} KiB and "
+             f"WRITE_SIZE {cal.get('WRITE_SIZE', 0):.6g} KiB (factors {ff and round(ff, 3)}, {wf and round(wf, 3)})", "",
+             "| kernel | HBM read (GB) | HBM write (GB) | L2 hit % | VALU busy % | VALU util % | VALU instr / CU-cycle "
+             "| LDS conflict cycles / CU-cycle |", "|---|---|---|---|---|---|---|---|"]
+    for k in sorted(m):
+        d = m[k]
+        cyc = d.get("GRBM_GUI_ACTIVE", 0) / xcds
+        f = lambda x: "" if x is None else f"{x:.3g}"
+        rd = d["FETCH_SIZE"] * 1024 * ff / 1e9 if ff and "FETCH_SIZE" in d else None
+        wr = d["WRITE_SIZE"] * 1024 * wf / 1e9 if wf and "WRITE_SIZE" in d else None
+        hit = (100 * d["TCC_HIT_sum"] / (d["TCC_HIT_sum"] + d["TCC_MISS_sum"])
+               if d.get("TCC_HIT_sum", 0) + d.get("TCC_MISS_sum", 0) > 0 else None)
+        busy = 100 * d["SQ_ACTIVE_INST_VALU"] / cus / cyc if cyc and "SQ_ACTIVE_INST_VALU" in d else None
+        util = (100 * d["SQ_THREAD_CYCLES_VALU"] / (64 * d["SQ_ACTIVE_INST_VALU"])
+                if d.get("SQ_ACTIVE_INST_VALU") else None)
+        ipc = d["SQ_INSTS_VALU"] / cus / cyc if cyc and "SQ_INSTS_VALU" in d else None
+        ldsc = d["SQ_LDS_BANK_CONFLICT"] / cus / cyc if cyc and "SQ_LDS_BANK_CONFLICT" in d else None
+        lines.append(f"| {k} | {f(rd)} | {f(wr)} | {f(hit)} | {f(busy)} | {f(util)} | {f(ipc)} | {f(ldsc)} |")
+    return "\n".join(lines)
+
+
 def _rays(geo, angles):
     """Ray end points in voxel-cell coordinates for the listed views (FP64)."""
     nz, ny, nx = geo.nVoxel
@@ -289,12 +341,18 @@ def main():
     ap.add_argument("--profile-summary", metavar="DB",
                     help="only print markdown tables of a rocprofv3 results database and exit")
     ap.add_argument("--top", type=int, default=12, help="kernels listed by --profile-summary")
+    ap.add_argument("--profile-derived", metavar="DB", nargs="+",
+                    help="only print derived per-kernel metrics (HBM bytes, L2 hit rate, VALU busy and "
+                         "utilisation, LDS conflicts) from rocprofv3 counter databases and exit")
     ap.add_argument("--profile-run", action="store_true",
                     help="run each rated kernel once on the workload (after a 1 GiB calibration copy) and exit: "
                          "the program profiled for kernel traces and counters")
     args = ap.parse_args()
     if args.profile_summary:
         print(profile_summary(args.profile_summary, top=args.top))
+        return
+    if args.profile_derived:
+        print(profile_derived(args.profile_derived))
         return
     if args.copy_calibration:
         import torch
