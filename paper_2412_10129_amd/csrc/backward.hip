@@ -64,8 +64,17 @@ __device__ __forceinline__ void brick_origin(const BrickMap& m, int b, int& bx, 
 }
 
 // Pixel range whose rays may cross the voxel-centre-coordinate box
-// [lo, hi] (per axis x, y, z): bounding box of the 8 projected corners,
-// widened by one pixel and clamped to the detector.  Returns false if empty.
+// [lo, hi] (per axis x, y, z): the pixel centres inside the bounding box of
+// the 8 projected corners (the box's silhouette is their convex hull, so a
+// ray through a centre outside it misses the box), widened by FOOT_EPS pixel
+// against the FP32 rounding of the projection (about 1e-4 pixel; a ray that
+// close to the box lies within 0.01 pixel of it, some 100 FP32 position
+// rounding units, so a sample the FP32 walk might still place in the box is
+// never left out), clamped to the detector.  Returns false if empty.
+#ifndef CTMI_BWD_FOOT_EPS
+#define CTMI_BWD_FOOT_EPS 0.01f
+#endif
+constexpr float FOOT_EPS = CTMI_BWD_FOOT_EPS;
 __device__ __forceinline__ bool footprint(const ViewGeo& g, const float lo[3], const float hi[3],
                                           const DetDims& det, int& u0, int& u1, int& v0, int& v1)
 {
@@ -89,10 +98,10 @@ __device__ __forceinline__ bool footprint(const ViewGeo& g, const float lo[3], c
     vmin = fminf(fmaxf(vmin, -2.0f), (float)det.nv + 1.0f);
     umax = fminf(fmaxf(umax, -2.0f), (float)det.nu + 1.0f);
     vmax = fminf(fmaxf(vmax, -2.0f), (float)det.nv + 1.0f);
-    u0 = max((int)__builtin_floorf(umin) - 1, 0);
-    v0 = max((int)__builtin_floorf(vmin) - 1, 0);
-    u1 = min((int)__builtin_ceilf(umax) + 1, det.nu - 1);
-    v1 = min((int)__builtin_ceilf(vmax) + 1, det.nv - 1);
+    u0 = max((int)__builtin_ceilf(umin - FOOT_EPS), 0);
+    v0 = max((int)__builtin_ceilf(vmin - FOOT_EPS), 0);
+    u1 = min((int)__builtin_floorf(umax + FOOT_EPS), det.nu - 1);
+    v1 = min((int)__builtin_floorf(vmax + FOOT_EPS), det.nv - 1);
     return u0 <= u1 && v0 <= v1;
 }
 
@@ -488,32 +497,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const int sx = ax.step, sy = ay.step * BX, sz = az.step * BX * BY;
                 const float yl = t_y[r];
                 float acur = astart;
+                const float fx = (float)ax.step, fy = (float)ay.step, fz = (float)az.step;
                 asm volatile("" ::"v"(yl), "v"(acur), "v"(aend), "v"(li));
+                // the crossing axis advances by selects, so lanes walking
+                // different rays do not diverge over it
                 for (int step = 0; step < BX + BY + BZ + 3; ++step) {
                     const float an = fminf(anx, fminf(any, anz));
                     const float ae = fminf(an, aend);
                     acc_add(&acc[li], fmaxf(ae - acur, 0.0f) * yl);
                     if (an >= aend) break;
                     acur = an;
-                    if (an == anx) {
-                        ix += ax.step;
-                        if (ix < x0 || ix >= x1) break;
-                        li += sx;
-                        qx += (float)ax.step;
-                        anx = plane_alpha(ax, qx);
-                    } else if (an == any) {
-                        iy += ay.step;
-                        if (iy < y0 || iy >= y1) break;
-                        li += sy;
-                        qy += (float)ay.step;
-                        any = plane_alpha(ay, qy);
-                    } else {
-                        iz += az.step;
-                        if (iz < z0 || iz >= z1) break;
-                        li += sz;
-                        qz += (float)az.step;
-                        anz = plane_alpha(az, qz);
-                    }
+                    const bool mx = an == anx, my = !mx && an == any, mz = !mx && !my;
+                    ix += mx ? ax.step : 0;
+                    iy += my ? ay.step : 0;
+                    iz += mz ? az.step : 0;
+                    if (ix < x0 || ix >= x1 || iy < y0 || iy >= y1 || iz < z0 || iz >= z1) break;
+                    li += mx ? sx : (my ? sy : sz);
+                    qx += mx ? fx : 0.0f;
+                    qy += my ? fy : 0.0f;
+                    qz += mz ? fz : 0.0f;
+                    anx = mx ? plane_alpha(ax, qx) : anx;
+                    any = my ? plane_alpha(ay, qy) : any;
+                    anz = mz ? plane_alpha(az, qz) : anz;
                 }
             }
             __syncthreads();

@@ -344,40 +344,56 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
         __syncthreads();
         load_box(box, vol, v, b);
         __syncthreads();
-        while (w.alive) {
-            const int ia = a == 0 ? w.ix : (a == 1 ? w.iy : w.iz);
-            if (dir > 0 ? ia >= c1 : ia < c0) break;     // the ray has left this slab
-            const int lx = w.ix - b.o[0], ly = w.iy - b.o[1], lz = w.iz - b.o[2];
-            const bool in = (unsigned)lx < (unsigned)b.e[0] && (unsigned)ly < (unsigned)b.e[1] &&
-                            (unsigned)lz < (unsigned)b.e[2];
-            const float val = in ? box[(lz * b.e[1] + ly) * b.e[0] + lx] : vol[w.idx];
-            const float an = fminf(w.anx, fminf(w.any, w.anz));
-            const float ae = fminf(an, w.amax);
-            w.acc = __builtin_fmaf(fmaxf(ae - w.acur, 0.0f), val, w.acc);
-            if (an >= w.amax || --w.left <= 0) {
+        if (w.alive) {
+            // walk the slab on box coordinates: the LDS offset follows the
+            // cell, each step advances the crossing axis by selects (no
+            // divergent branches), and a cell outside the box (a box clipped
+            // to the LDS capacity) is read from global memory instead
+            int lx = w.ix - b.o[0], ly = w.iy - b.o[1], lz = w.iz - b.o[2];
+            int loff = (lz * b.e[1] + ly) * b.e[0] + lx;
+            const int ox = ax.step, oy = ay.step * b.e[0], oz = az.step * b.e[0] * b.e[1];
+            const float fx = (float)ax.step, fy = (float)ay.step, fz = (float)az.step;
+            for (;;) {
+                // the ray has left this slab once its dominant coordinate leaves the box
+                const int ld = a == 0 ? lx : (a == 1 ? ly : lz);
+                const int ed = a == 0 ? b.e[0] : (a == 1 ? b.e[1] : b.e[2]);
+                if ((unsigned)ld >= (unsigned)ed) break;
+                const bool in = (unsigned)lx < (unsigned)b.e[0] && (unsigned)ly < (unsigned)b.e[1] &&
+                                (unsigned)lz < (unsigned)b.e[2];
+                float val = box[in ? loff : 0];
+                // keep the LDS read a plain ds_read: the global fallback below
+                // must not be merged with it into one generic (flat) load
+                asm volatile("" : "+v"(val));
+                if (!in) val = vol[w.idx];
+                const float an = fminf(w.anx, fminf(w.any, w.anz));
+                const float ae = fminf(an, w.amax);
+                w.acc = __builtin_fmaf(fmaxf(ae - w.acur, 0.0f), val, w.acc);
+                if (an >= w.amax || --w.left <= 0) {
+                    w.alive = false;
+                    break;
+                }
+                w.acur = an;
+                const bool mx = an == w.anx, my = !mx && an == w.any, mz = !mx && !my;
+                lx += mx ? ax.step : 0;
+                ly += my ? ay.step : 0;
+                lz += mz ? az.step : 0;
+                loff += mx ? ox : (my ? oy : oz);
+                w.idx += mx ? sx : (my ? sy : sz);
+                w.qx += mx ? fx : 0.0f;
+                w.qy += my ? fy : 0.0f;
+                w.qz += mz ? fz : 0.0f;
+                w.anx = mx ? plane_alpha(ax, w.qx) : w.anx;
+                w.any = my ? plane_alpha(ay, w.qy) : w.any;
+                w.anz = mz ? plane_alpha(az, w.qz) : w.anz;
+            }
+            w.ix = lx + b.o[0];
+            w.iy = ly + b.o[1];
+            w.iz = lz + b.o[2];
+            // a step out of the volume ends the ray (it crosses the volume's
+            // face at amax, so this only guards rounding)
+            if ((unsigned)w.ix >= (unsigned)v.nx || (unsigned)w.iy >= (unsigned)v.ny ||
+                (unsigned)w.iz >= (unsigned)v.nz)
                 w.alive = false;
-                break;
-            }
-            w.acur = an;
-            if (an == w.anx) {
-                w.ix += ax.step;
-                if ((unsigned)w.ix >= (unsigned)v.nx) w.alive = false;
-                w.idx += sx;
-                w.qx += (float)ax.step;
-                w.anx = plane_alpha(ax, w.qx);
-            } else if (an == w.any) {
-                w.iy += ay.step;
-                if ((unsigned)w.iy >= (unsigned)v.ny) w.alive = false;
-                w.idx += sy;
-                w.qy += (float)ay.step;
-                w.any = plane_alpha(ay, w.qy);
-            } else {
-                w.iz += az.step;
-                if ((unsigned)w.iz >= (unsigned)v.nz) w.alive = false;
-                w.idx += sz;
-                w.qz += (float)az.step;
-                w.anz = plane_alpha(az, w.qz);
-            }
         }
     }
     // anything left (never expected) finishes from global memory
