@@ -297,6 +297,21 @@ int ctmi_em_update(float* x, const float* v, const float* bp, int64_t n, void* s
 int ctmi_fov_sq_err(const ctmi_plan* plan, const float* x, const float* gt, double* out, void* ws,
                     size_t ws_bytes, void* stream);
 
+/* ------------------------------------------- allocation-free calls -- */
+/* ctmi_backproject without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The interpolated adjoint's brick
+ * shells go to a scratch array inside the library instead: 160 MiB on every
+ * GPU that loads the library, held until the process ends, enough for
+ * volumes of up to 75 846 bricks of 16x16x8 voxels (a 512^3 volume has
+ * 65 536); larger volumes return CTMI_EWORKSPACE.  All calls on one GPU
+ * share that GPU's scratch, so calls that overlap on one GPU (on different
+ * streams) race and must not be issued; each call writes all the scratch it
+ * reads, so nothing needs clearing.  The Siddon and FDK backprojectors need
+ * no scratch.  Otherwise exactly as ctmi_backproject (same kernels). */
+int ctmi_backproject_noalloc(const ctmi_plan* plan, int bp, const float* proj, float* vol, int64_t view0,
+                             int64_t nviews, float beta, void* stream);
+
 /* ------------------------------------------------ curved detectors -- */
 /* A cylindrically curved detector (section 2.4 on geometric flexibility:
  * curved detectors, taken in through a flattening transformation).  The

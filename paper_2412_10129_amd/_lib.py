@@ -92,6 +92,7 @@ _SIGS = {
     "ctmi_plan_destroy": (c_int, [c_p]),
     "ctmi_forward": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),
     "ctmi_backproject": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_f, c_p, ctypes.c_size_t, c_p]),
+    "ctmi_backproject_noalloc": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_f, c_p]),
     "ctmi_workspace_size": (c_int, [c_p, c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "ctmi_stream_check": (c_int, [c_p]),
     "ctmi_fdk_filter": (c_int, [c_p, c_int, c_p, c_p, c_i64, c_i64, c_p]),

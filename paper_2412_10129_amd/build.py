@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctmi.so")
-SOURCES = ["ctmi.cpp", "forward.hip", "backward.hip", "fdk.hip", "vecops.hip", "curved.hip", "ceilings.hip", "unet.hip",
+SOURCES = ["ctmi.cpp", "forward.hip", "backward.hip", "fdk.hip", "vecops.hip", "curved.hip", "ceilings.hip", "noalloc.hip", "unet.hip",
            "unet_abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
