@@ -29,7 +29,7 @@ def _addr(t: torch.Tensor, i: int, j: int) -> int:
 
 
 def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Optional[torch.Tensor] = None,
-         x0: Optional[torch.Tensor] = None, sync: bool = True, snapshots=()):
+         x0: Optional[torch.Tensor] = None, sync: bool = True, snapshots=(), callback=None):
     """CGLS (Hestenes-Stiefel; the Krylov solvers of section 2.2.1).
 
     x0 = 0 (or the given start); r = b - A x0; s = A^T r; p = s; gamma = |s|^2;
@@ -40,7 +40,9 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
     x_gt, the squared error and voxel count inside the FOV (the residual and
     error-norm histories of section 2.2.3).  With sync=False, hist holds the
     device tensors instead of host arrays.  hist["snapshots"][k] is a copy of
-    the iterate after k iterations for every k in `snapshots`.
+    the iterate after k iterations for every k in `snapshots`.  `callback(k,
+    x)`, if given, runs on the host after iteration k (k = 1..niter) has been
+    queued, with the iterate's device tensor (it may synchronize).
     """
     dev = plan.device
     vol_shape, proj_shape = plan.vol_shape, plan.proj_shape()
@@ -73,6 +75,8 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
             plan.fov_sq_err(x, x_gt, err[k])
         if k + 1 in snaps:
             snaps[k + 1] = x.clone()
+        if callback is not None:
+            callback(k + 1, x)
     hist = {"scalars": sc, "err": err, "snapshots": snaps}
     if sync:
         h = sc.cpu().numpy()

@@ -383,6 +383,10 @@ struct InterpRay {
 __device__ __forceinline__ bool interp_ray(const ViewGeo64& g, int iu, int iv, const VolDims& v, float ds,
                                            float inv_ds, InterpRay& r)
 {
+    // a ray that misses returns with an empty sample range anchored at 0
+    r.k0 = 0;
+    r.k1 = -1;
+    r.kc = 0;
     double S[3], d[3];
     pixel_ray64(g, iu, iv, S, d);
     const double x = d[0] * v.hx, y = d[1] * v.hy, z = d[2] * v.hz;

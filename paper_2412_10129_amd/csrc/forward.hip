@@ -191,55 +191,115 @@ __device__ __forceinline__ bool make_box(const int lo[3], const int hi[3], const
     return b.e[0] * b.e[1] * b.e[2] <= BOXCAP;
 }
 
-// Flat loop over the box with x fastest (coalesced global reads).  The
-// index is split into (x, y, z) with float reciprocals: floor((i + 1/2) r),
-// r = fl(1/e), equals i / e for every i < 2^22, because (i + 1/2)/e is at
-// least 1/(2e) away from an integer while the FP32 error is below
-// (i + 1/2) 2^-23 / e.
+// Box staging by rows.  A row is the box's x extent W = e[0] at one (y, z);
+// thread t takes column t mod W of rows t div W + m RG (pass m), RG =
+// floor(256 / W) whole rows per pass, so consecutive threads load
+// consecutive x (coalesced global reads, consecutive LDS words) and a
+// thread's column and its x bounds check stay fixed.  From one pass to the
+// next a thread's row advances by RG = RGz e[1] + RGy, so its (y, z) and its
+// global index advance by constants, with one carry from y into z.  Initial
+// quotients use float reciprocals: floor((i + 1/2) r), r = fl(1/e), equals
+// i div e for every i < 2^22, because (i + 1/2)/e is at least 1/(2e) away
+// from an integer while the FP32 error is below (i + 1/2) 2^-23 / e.  The
+// global index is kept modulo 2^32 (a cell inside the volume has an index
+// below 2^31, checked at plan creation).  A box wider than 256 along x (not
+// produced by tile-sized bundles) is staged element by element.
+struct Stage {
+    int ly, lz;        // this thread's current row as box (y, z); lz >= e[2] once past the last row
+    unsigned gi;       // global index of the current element (mod 2^32)
+    int li;            // its LDS index
+    int rgy, rgz;      // pass advance
+    unsigned d1, d2;   // global index advance, and the extra on a carry into z
+    int lstep;         // LDS index advance
+    bool xok;          // this thread holds a column, inside the volume along x
+};
+
+__device__ __forceinline__ Stage stage_of(const Box& b, const VolDims& v)
+{
+    Stage s;
+    const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
+    const int rg = (int)__builtin_floorf(256.5f * r0);
+    const int t = (int)threadIdx.x;
+    const int tr = (int)__builtin_floorf(((float)t + 0.5f) * r0);
+    const int tx = t - tr * b.e[0];
+    s.lz = (int)__builtin_floorf(((float)tr + 0.5f) * r1);
+    s.ly = tr - s.lz * b.e[1];
+    if (tr >= rg) s.lz = b.e[2];   // no column for this thread
+    s.rgz = (int)__builtin_floorf(((float)rg + 0.5f) * r1);
+    s.rgy = rg - s.rgz * b.e[1];
+    const unsigned nx = (unsigned)v.nx, nxy = (unsigned)v.nx * (unsigned)v.ny;
+    const int gx = b.o[0] + tx;
+    s.xok = (unsigned)gx < nx;
+    s.gi = (unsigned)(b.o[2] + s.lz) * nxy + (unsigned)(b.o[1] + s.ly) * nx + (unsigned)gx;
+    s.d1 = (unsigned)s.rgz * nxy + (unsigned)s.rgy * nx;
+    s.d2 = nxy - (unsigned)b.e[1] * nx;
+    s.li = tr * b.e[0] + tx;
+    s.lstep = rg * b.e[0];
+    return s;
+}
+
+// value of the current element (0 outside the volume), then advance a pass
+__device__ __forceinline__ float stage_next(Stage& s, const float* __restrict__ vol, const VolDims& v, const Box& b)
+{
+    float val = 0.0f;
+    if (s.xok && (unsigned)(b.o[1] + s.ly) < (unsigned)v.ny && (unsigned)(b.o[2] + s.lz) < (unsigned)v.nz)
+        val = vol[s.gi];
+    s.ly += s.rgy;
+    const bool c = s.ly >= b.e[1];
+    s.ly -= c ? b.e[1] : 0;
+    s.lz += s.rgz + (c ? 1 : 0);
+    s.gi += s.d1 + (c ? s.d2 : 0u);
+    s.li += s.lstep;
+    return val;
+}
+
+// element i of a box wider than 256 along x
+__device__ __forceinline__ float element_value(const float* __restrict__ vol, const VolDims& v, const Box& b, int i)
+{
+    const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
+    const int q = (int)__builtin_floorf(((float)i + 0.5f) * r0);
+    const int lx = i - (int)__umul24(q, b.e[0]);
+    const int lz = (int)__builtin_floorf(((float)q + 0.5f) * r1);
+    const int ly = q - (int)__umul24(lz, b.e[1]);
+    const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = b.o[2] + lz;
+    float val = 0.0f;
+    if ((unsigned)gx < (unsigned)v.nx && (unsigned)gy < (unsigned)v.ny && (unsigned)gz < (unsigned)v.nz)
+        val = vol[(__umul24((unsigned)gz, (unsigned)v.ny) + (unsigned)gy) * (unsigned)v.nx + (unsigned)gx];
+    return val;
+}
+
 __device__ __forceinline__ void load_box(float* box, const float* __restrict__ vol, const VolDims& v, const Box& b)
 {
-    const int n = b.e[0] * b.e[1] * b.e[2];
-    const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int r = (int)__builtin_floorf(((float)i + 0.5f) * r0);
-        const int lx = i - (int)__umul24(r, b.e[0]);
-        const int lz = (int)__builtin_floorf(((float)r + 0.5f) * r1);
-        const int ly = r - (int)__umul24(lz, b.e[1]);
-        const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = b.o[2] + lz;
-        float val = 0.0f;
-        // the volume has fewer than 2^31 voxels (checked at plan creation), so
-        // the linear index fits 32 bits
-        if ((unsigned)gx < (unsigned)v.nx && (unsigned)gy < (unsigned)v.ny && (unsigned)gz < (unsigned)v.nz)
-            val = vol[(__umul24((unsigned)gz, (unsigned)v.ny) + (unsigned)gy) * (unsigned)v.nx + (unsigned)gx];
-        box[i] = val;
+    if (b.e[0] > 256) {
+        const int n = b.e[0] * b.e[1] * b.e[2];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) box[i] = element_value(vol, v, b, i);
+        return;
+    }
+    Stage s = stage_of(b, v);
+    while (s.lz < b.e[2]) {
+        const int li = s.li;
+        box[li] = stage_next(s, vol, v, b);
     }
 }
 
-// Software-pipelined staging: the first PF * 256 elements of the next slab's
-// box are loaded into registers (element i = threadIdx.x + 256 m in
-// r[m]) while the current slab is sampled, then written to LDS; any
-// elements beyond that are read directly when the box is written.  Same
-// index split as load_box.
+// Software-pipelined staging: the first PF passes of the next slab's box
+// are loaded into registers while the current slab is sampled, then written
+// to LDS; any further passes are read directly when the box is written.
 template <int PF>
 __device__ __forceinline__ void fetch_box(float (&r)[PF], const float* __restrict__ vol, const VolDims& v,
                                           const Box& b, bool on)
 {
-    const int n = on ? b.e[0] * b.e[1] * b.e[2] : 0;
-    const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
+    if (on && b.e[0] <= 256) {
+        Stage s = stage_of(b, v);
 #pragma unroll
-    for (int m = 0; m < PF; ++m) {
-        const int i = (int)threadIdx.x + 256 * m;
-        float val = 0.0f;
-        if (i < n) {
-            const int q = (int)__builtin_floorf(((float)i + 0.5f) * r0);
-            const int lx = i - (int)__umul24(q, b.e[0]);
-            const int lz = (int)__builtin_floorf(((float)q + 0.5f) * r1);
-            const int ly = q - (int)__umul24(lz, b.e[1]);
-            const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = b.o[2] + lz;
-            if ((unsigned)gx < (unsigned)v.nx && (unsigned)gy < (unsigned)v.ny && (unsigned)gz < (unsigned)v.nz)
-                val = vol[(__umul24((unsigned)gz, (unsigned)v.ny) + (unsigned)gy) * (unsigned)v.nx + (unsigned)gx];
+        for (int m = 0; m < PF; ++m) {
+            const bool row = s.lz < b.e[2];
+            const float val = stage_next(s, vol, v, b);
+            r[m] = row ? val : 0.0f;
         }
-        r[m] = val;
+    } else {
+#pragma unroll
+        for (int m = 0; m < PF; ++m) r[m] = 0.0f;
     }
 }
 
@@ -247,35 +307,104 @@ template <int PF>
 __device__ __forceinline__ void put_box(float* box, const float (&r)[PF], const float* __restrict__ vol,
                                         const VolDims& v, const Box& b, bool on)
 {
-    const int n = on ? b.e[0] * b.e[1] * b.e[2] : 0;
+    if (!on) return;
+    if (b.e[0] > 256) {
+        load_box(box, vol, v, b);
+        return;
+    }
+    Stage s = stage_of(b, v);
 #pragma unroll
     for (int m = 0; m < PF; ++m) {
-        const int i = (int)threadIdx.x + 256 * m;
-        if (i < n) box[i] = r[m];
+        if (s.lz < b.e[2]) box[s.li] = r[m];
+        s.ly += s.rgy;
+        const bool c = s.ly >= b.e[1];
+        s.ly -= c ? b.e[1] : 0;
+        s.lz += s.rgz + (c ? 1 : 0);
+        s.gi += s.d1 + (c ? s.d2 : 0u);
+        s.li += s.lstep;
     }
-    if (n > 256 * PF) {
-        const float r0 = 1.0f / (float)b.e[0], r1 = 1.0f / (float)b.e[1];
-        for (int i = (int)threadIdx.x + 256 * PF; i < n; i += 256) {
-            const int q = (int)__builtin_floorf(((float)i + 0.5f) * r0);
-            const int lx = i - (int)__umul24(q, b.e[0]);
-            const int lz = (int)__builtin_floorf(((float)q + 0.5f) * r1);
-            const int ly = q - (int)__umul24(lz, b.e[1]);
-            const int gx = b.o[0] + lx, gy = b.o[1] + ly, gz = b.o[2] + lz;
-            float val = 0.0f;
-            if ((unsigned)gx < (unsigned)v.nx && (unsigned)gy < (unsigned)v.ny && (unsigned)gz < (unsigned)v.nz)
-                val = vol[(__umul24((unsigned)gz, (unsigned)v.ny) + (unsigned)gy) * (unsigned)v.nx + (unsigned)gx];
-            box[i] = val;
-        }
+    while (s.lz < b.e[2]) {
+        const int li = s.li;
+        box[li] = stage_next(s, vol, v, b);
     }
 }
 
 // ------------------------------------------------------------------ Siddon
-struct SiddonWalk {
-    int ix, iy, iz, idx;
-    float qx, qy, qz, anx, any, anz, acur, amax, acc;
-    int left;  // iteration budget
-    bool alive;
+// The Siddon sum is taken one layer at a time along the tile's dominant
+// axis a (a layer is one cell thick along a; the two other axes are b and
+// c).  Inside a layer a ray whose direction has |d_b| and |d_c| below
+// 0.99 |d_a| crosses at most one plane of b and one of c, so it passes
+// through at most three cells; the three lengths follow from the two next
+// crossing parameters by a min, a max and two clamps, and the three cells
+// from which crossings fall inside the layer.  Every lane of a wave then
+// does the same work per layer (no data-dependent branch), instead of one
+// loop trip per crossing with the crossing axis chosen per lane.  The
+// crossing parameters are the plane-by-plane walk's (plane q at q inv + c,
+// FP32), so the lengths are that walk's, in the same cells.
+//
+// Two cases leave the three-cell form: a tile holding a ray steeper than
+// 0.99 along b or c (it may cross two planes of one axis in a layer) and a
+// ray whose path through a slab leaves the staged box (a box clipped to the
+// LDS capacity).  Those lanes walk the layer plane by plane, reading cells
+// outside the box from global memory.
+__device__ __forceinline__ float sid_cell(const float* box, const float* __restrict__ vol, const VolDims& v,
+                                          const Box& bx, int x, int y, int z)
+{
+    const int lx = x - bx.o[0], ly = y - bx.o[1], lz = z - bx.o[2];
+    if ((unsigned)lx < (unsigned)bx.e[0] && (unsigned)ly < (unsigned)bx.e[1] && (unsigned)lz < (unsigned)bx.e[2])
+        return box[(lz * bx.e[1] + ly) * bx.e[0] + lx];
+    if ((unsigned)x < (unsigned)v.nx && (unsigned)y < (unsigned)v.ny && (unsigned)z < (unsigned)v.nz)
+        return vol[(__umul24((unsigned)z, (unsigned)v.ny) + (unsigned)y) * (unsigned)v.nx + (unsigned)x];
+    return 0.0f;
+}
+
+template <typename T>
+__device__ __forceinline__ T pick3(int i, T v0, T v1, T v2)
+{
+    return i == 0 ? v0 : (i == 1 ? v1 : v2);
+}
+
+__device__ __forceinline__ SiddonAxis pick_axis(int i, const SiddonAxis& x, const SiddonAxis& y, const SiddonAxis& z)
+{
+    SiddonAxis r;
+    r.inv = pick3(i, x.inv, y.inv, z.inv);
+    r.c = pick3(i, x.c, y.c, z.c);
+    r.step = pick3(i, x.step, y.step, z.step);
+    return r;
+}
+
+// One ray's position in the layer walk: current parameter, end of the
+// clipped ray, and per non-dominant axis the plane coordinate of the next
+// crossing (an exact integer in FP32) with its parameter.
+struct LayerRay {
+    float acur, aend, qb, qc, anb, anc, acc;
 };
+
+// Plane-by-plane walk of one layer (cell k along a) up to parameter ae.
+__device__ __forceinline__ void walk_layer(LayerRay& r, float ae, int k, int a, const SiddonAxis& B,
+                                           const SiddonAxis& C, const float* box, const float* __restrict__ vol,
+                                           const VolDims& v, const Box& bx)
+{
+    // at most two crossings of each of b and c fall inside one layer of a
+    // ray that runs within 45 degrees of a (the tile's dominant axis); the
+    // bound only caps the loop
+    for (int it = 0; it < 8 && r.acur < ae; ++it) {
+        const float an = fminf(fminf(r.anb, r.anc), ae);
+        const int ib = (int)r.qb - (B.step > 0), ic = (int)r.qc - (C.step > 0);
+        const int x = a == 0 ? k : ib, y = a == 1 ? k : (a == 0 ? ib : ic), z = a == 2 ? k : ic;
+        r.acc = __builtin_fmaf(an - r.acur, sid_cell(box, vol, v, bx, x, y, z), r.acc);
+        r.acur = an;
+        if (an >= ae) break;
+        if (r.anb <= r.anc) {
+            r.qb += (float)B.step;
+            r.anb = __builtin_fmaf(r.qb, B.inv, B.c);
+        } else {
+            r.qc += (float)C.step;
+            r.anc = __builtin_fmaf(r.qc, C.inv, C.c);
+        }
+    }
+    r.acur = ae;
+}
 
 __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict__ vol, float* __restrict__ proj,
                                                         const ViewGeo* __restrict__ tab,
@@ -295,31 +424,57 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
     const SiddonAxis ax = siddon_axis(S[0], d[0]);
     const SiddonAxis ay = siddon_axis(S[1], d[1]);
     const SiddonAxis az = siddon_axis(S[2], d[2]);
-    SiddonWalk w;
-    w.acc = 0.0f;
-    w.amax = a_hi;
-    float amin = a_lo;
-    bool hit = slab_clip(ax, S[0], 0.0f, (float)v.nx, amin, w.amax);
-    hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, w.amax);
-    hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, w.amax);
-    w.alive = active && hit && amin < w.amax;
-    w.ix = ordered_cell(ax, S[0], d[0], amin, 0, v.nx);
-    w.iy = ordered_cell(ay, S[1], d[1], amin, 0, v.ny);
-    w.iz = ordered_cell(az, S[2], d[2], amin, 0, v.nz);
-    w.qx = (float)(w.ix + (ax.step > 0));
-    w.qy = (float)(w.iy + (ay.step > 0));
-    w.qz = (float)(w.iz + (az.step > 0));
-    w.anx = plane_alpha(ax, w.qx);
-    w.any = plane_alpha(ay, w.qy);
-    w.anz = plane_alpha(az, w.qz);
-    w.idx = (w.iz * v.ny + w.iy) * v.nx + w.ix;
-    w.acur = amin;
-    w.left = v.nx + v.ny + v.nz + 3;
-    const int sx = ax.step, sy = ay.step * v.nx, sz = az.step * v.nx * v.ny;
+    float amin = a_lo, amax = a_hi;
+    bool hit = slab_clip(ax, S[0], 0.0f, (float)v.nx, amin, amax);
+    hit &= slab_clip(ay, S[1], 0.0f, (float)v.ny, amin, amax);
+    hit &= slab_clip(az, S[2], 0.0f, (float)v.nz, amin, amax);
+    const bool alive = active && hit && amin < amax;
 
     int a, dir;
     tile_axis(g, det, tu0, tv0, a, dir);
-    const int na = a == 0 ? v.nx : (a == 1 ? v.ny : v.nz);
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    const SiddonAxis A = pick_axis(a, ax, ay, az), B = pick_axis(b, ax, ay, az), C = pick_axis(c, ax, ay, az);
+    const float Sa = pick3(a, S[0], S[1], S[2]), Da = pick3(a, d[0], d[1], d[2]);
+    const float Sb = pick3(b, S[0], S[1], S[2]), Db = pick3(b, d[0], d[1], d[2]);
+    const float Sc = pick3(c, S[0], S[1], S[2]), Dc = pick3(c, d[0], d[1], d[2]);
+    const int na = pick3(a, v.nx, v.ny, v.nz), nb = pick3(b, v.nx, v.ny, v.nz), nc = pick3(c, v.nx, v.ny, v.nz);
+
+    // a ray that runs against the tile's direction along a (only possible
+    // at extreme fan angles) is walked plane by plane from global memory at
+    // the end instead
+    const bool odd = alive && A.step != dir;
+    const bool lay = alive && !odd;
+    LayerRay r;
+    r.acc = 0.0f;
+    r.acur = lay ? amin : 0.0f;
+    r.aend = lay ? amax : 0.0f;
+    {
+        const int ib = ordered_cell(B, Sb, Db, amin, 0, nb), ic = ordered_cell(C, Sc, Dc, amin, 0, nc);
+        r.qb = (float)(ib + (B.step > 0));
+        r.qc = (float)(ic + (C.step > 0));
+        // a parallel axis has inv = 0 and c = inf, so its crossings stay at inf
+        r.anb = lay ? __builtin_fmaf(r.qb, B.inv, B.c) : CTMI_INF;
+        r.anc = lay ? __builtin_fmaf(r.qc, C.inv, C.c) : CTMI_INF;
+    }
+    // the wave's layer range (cells along a that some lane's ray reaches)
+    int klo = 0x7fffffff, khi = -1;
+    if (lay) {
+        const float p0 = __builtin_fmaf(amin, Da, Sa), p1 = __builtin_fmaf(amax, Da, Sa);
+        klo = max((int)__builtin_floorf(fminf(p0, p1)) - 1, 0);
+        khi = min((int)__builtin_floorf(fmaxf(p0, p1)) + 1, na - 1);
+    }
+    // the three-cell form needs every ray of the wave below 0.99 along b and c
+    bool steep = lay && (fabsf(Db) > 0.99f * fabsf(Da) || fabsf(Dc) > 0.99f * fabsf(Da));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        klo = min(klo, __shfl_xor(klo, off));
+        khi = max(khi, __shfl_xor(khi, off));
+    }
+    // (the same in every lane now: keep them in scalar registers)
+    klo = __builtin_amdgcn_readfirstlane(klo);
+    khi = __builtin_amdgcn_readfirstlane(khi);
+    const bool wave_steep = __any(steep);
+
     const int nslab = (na + SLAB - 1) / SLAB;
     const int clo[3] = {0, 0, 0}, chi[3] = {v.nx - 1, v.ny - 1, v.nz - 1};
 
@@ -339,91 +494,118 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
             lo[i] = i == a ? c0 : lo[i];
             hi[i] = i == a ? c1 - 1 : hi[i];
         }
-        Box b;
-        if (!make_box(lo, hi, clo, chi, a, b)) continue;
+        Box bx;
+        if (!make_box(lo, hi, clo, chi, a, bx)) continue;
+        // the box is the same in every lane: scalar registers
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            bx.o[i] = __builtin_amdgcn_readfirstlane(bx.o[i]);
+            bx.e[i] = __builtin_amdgcn_readfirstlane(bx.e[i]);
+        }
         __syncthreads();
-        load_box(box, vol, v, b);
+        load_box(box, vol, v, bx);
         __syncthreads();
-        if (w.alive) {
-            // walk the slab on box coordinates: the LDS offset follows the
-            // cell, each step advances the crossing axis by selects (no
-            // divergent branches), and a cell outside the box (a box clipped
-            // to the LDS capacity) is read from global memory instead
-            int lx = w.ix - b.o[0], ly = w.iy - b.o[1], lz = w.iz - b.o[2];
-            int loff = (lz * b.e[1] + ly) * b.e[0] + lx;
-            const int ox = ax.step, oy = ay.step * b.e[0], oz = az.step * b.e[0] * b.e[1];
-            const float fx = (float)ax.step, fy = (float)ay.step, fz = (float)az.step;
-            for (;;) {
-                // the ray has left this slab once its dominant coordinate leaves the box
-                const int ld = a == 0 ? lx : (a == 1 ? ly : lz);
-                const int ed = a == 0 ? b.e[0] : (a == 1 ? b.e[1] : b.e[2]);
-                if ((unsigned)ld >= (unsigned)ed) break;
-                const bool in = (unsigned)lx < (unsigned)b.e[0] && (unsigned)ly < (unsigned)b.e[1] &&
-                                (unsigned)lz < (unsigned)b.e[2];
-                float val = box[in ? loff : 0];
-                // keep the LDS read a plain ds_read: the global fallback below
-                // must not be merged with it into one generic (flat) load
-                asm volatile("" : "+v"(val));
-                if (!in) val = vol[w.idx];
-                const float an = fminf(w.anx, fminf(w.any, w.anz));
-                const float ae = fminf(an, w.amax);
-                w.acc = __builtin_fmaf(fmaxf(ae - w.acur, 0.0f), val, w.acc);
-                if (an >= w.amax || --w.left <= 0) {
-                    w.alive = false;
-                    break;
-                }
-                w.acur = an;
-                const bool mx = an == w.anx, my = !mx && an == w.any, mz = !mx && !my;
-                lx += mx ? ax.step : 0;
-                ly += my ? ay.step : 0;
-                lz += mz ? az.step : 0;
-                loff += mx ? ox : (my ? oy : oz);
-                w.idx += mx ? sx : (my ? sy : sz);
-                w.qx += mx ? fx : 0.0f;
-                w.qy += my ? fy : 0.0f;
-                w.qz += mz ? fz : 0.0f;
-                w.anx = mx ? plane_alpha(ax, w.qx) : w.anx;
-                w.any = my ? plane_alpha(ay, w.qy) : w.any;
-                w.anz = mz ? plane_alpha(az, w.qz) : w.anz;
+        const int k0 = max(c0, klo), k1 = min(c1 - 1, khi);
+        if (k0 > k1) continue;   // no ray of this wave reaches these layers
+
+        // box strides (elements) and origins of the three axes
+        const int st_a = pick3(a, 1, bx.e[0], bx.e[0] * bx.e[1]);
+        const int st_b = pick3(b, 1, bx.e[0], bx.e[0] * bx.e[1]);
+        const int st_c = pick3(c, 1, bx.e[0], bx.e[0] * bx.e[1]);
+        const int oa = pick3(a, bx.o[0], bx.o[1], bx.o[2]);
+        const int ob = pick3(b, bx.o[0], bx.o[1], bx.o[2]), eb = pick3(b, bx.e[0], bx.e[1], bx.e[2]);
+        const int oc = pick3(c, bx.o[0], bx.o[1], bx.o[2]), ec = pick3(c, bx.e[0], bx.e[1], bx.e[2]);
+        // does this ray's path through the slab stay inside the box?  (the
+        // cells at both ends of its clipped stretch, one cell of margin; a
+        // ray with no stretch here sits the slab out)
+        bool inbox = true, idle = true;
+        int roff = 0;   // byte offset of the ray's (b, c) cell in a layer of the box
+        {
+            const float s0 = __builtin_fmaf((float)c0, A.inv, A.c), s1 = __builtin_fmaf((float)c1, A.inv, A.c);
+            const float t0 = fmaxf(fminf(s0, s1), r.acur), t1 = fminf(fmaxf(s0, s1), r.aend);
+            const int ib = (int)r.qb - (B.step > 0), ic = (int)r.qc - (C.step > 0);
+            if (t0 < t1) {
+                idle = false;
+                const float pb0 = __builtin_fmaf(t0, Db, Sb), pb1 = __builtin_fmaf(t1, Db, Sb);
+                const float pc0 = __builtin_fmaf(t0, Dc, Sc), pc1 = __builtin_fmaf(t1, Dc, Sc);
+                const int bl = max((int)__builtin_floorf(fminf(pb0, pb1)) - 1, 0);
+                const int bh = min((int)__builtin_floorf(fmaxf(pb0, pb1)) + 1, nb - 1);
+                const int cl = max((int)__builtin_floorf(fminf(pc0, pc1)) - 1, 0);
+                const int ch = min((int)__builtin_floorf(fmaxf(pc0, pc1)) + 1, nc - 1);
+                inbox = bl >= ob && bh < ob + eb && cl >= oc && ch < oc + ec && ib >= bl && ib <= bh &&
+                        ic >= cl && ic <= ch;
+                roff = inbox ? 4 * ((ib - ob) * st_b + (ic - oc) * st_c) : 0;
             }
-            w.ix = lx + b.o[0];
-            w.iy = ly + b.o[1];
-            w.iz = lz + b.o[2];
-            // a step out of the volume ends the ray (it crosses the volume's
-            // face at amax, so this only guards rounding)
-            if ((unsigned)w.ix >= (unsigned)v.nx || (unsigned)w.iy >= (unsigned)v.ny ||
-                (unsigned)w.iz >= (unsigned)v.nz)
-                w.alive = false;
+        }
+        const int DB = 4 * B.step * st_b, DC = 4 * C.step * st_c;
+        const char* boxb = (const char*)box;
+        for (int kk = 0; kk <= k1 - k0; ++kk) {
+            const int k = dir > 0 ? k0 + kk : k1 - kk;
+            const float aa = __builtin_fmaf((float)(k + (dir > 0)), A.inv, A.c);   // exit plane of layer k
+            const float ae = __builtin_amdgcn_fmed3f(aa, r.acur, r.aend);
+            const int loff = 4 * (k - oa) * st_a;
+            if (idle) {
+            } else if (inbox && !wave_steep) {
+                const bool cb = r.anb < ae, cc = r.anc < ae, bfirst = r.anb <= r.anc;
+                const float t1 = __builtin_amdgcn_fmed3f(bfirst ? r.anb : r.anc, r.acur, ae);
+                const float t2 = __builtin_amdgcn_fmed3f(bfirst ? r.anc : r.anb, r.acur, ae);
+                const int db = cb ? DB : 0, dc = cc ? DC : 0;
+                const int o0 = roff + loff;
+                const float v0 = *(const float*)(boxb + o0);
+                const float v1 = *(const float*)(boxb + o0 + (bfirst ? db : dc));
+                const float v2 = *(const float*)(boxb + o0 + db + dc);
+                r.acc = __builtin_fmaf(t1 - r.acur, v0, r.acc);
+                r.acc = __builtin_fmaf(t2 - t1, v1, r.acc);
+                r.acc = __builtin_fmaf(ae - t2, v2, r.acc);
+                r.acur = ae;
+                roff += db + dc;
+                r.qb = cb ? r.qb + (float)B.step : r.qb;
+                r.qc = cc ? r.qc + (float)C.step : r.qc;
+                r.anb = __builtin_fmaf(r.qb, B.inv, B.c);
+                r.anc = __builtin_fmaf(r.qc, C.inv, C.c);
+            } else {
+                walk_layer(r, ae, k, a, B, C, box, vol, v, bx);
+                const int ib = (int)r.qb - (B.step > 0), ic = (int)r.qc - (C.step > 0);
+                roff = 4 * ((ib - ob) * st_b + (ic - oc) * st_c);
+            }
         }
     }
-    // anything left (never expected) finishes from global memory
-    while (w.alive) {
-        const float an = fminf(w.anx, fminf(w.any, w.anz));
-        const float ae = fminf(an, w.amax);
-        w.acc = __builtin_fmaf(fmaxf(ae - w.acur, 0.0f), vol[w.idx], w.acc);
-        if (an >= w.amax || --w.left <= 0) break;
-        w.acur = an;
-        if (an == w.anx) {
-            w.ix += ax.step;
-            if ((unsigned)w.ix >= (unsigned)v.nx) break;
-            w.idx += sx;
-            w.qx += (float)ax.step;
-            w.anx = plane_alpha(ax, w.qx);
-        } else if (an == w.any) {
-            w.iy += ay.step;
-            if ((unsigned)w.iy >= (unsigned)v.ny) break;
-            w.idx += sy;
-            w.qy += (float)ay.step;
-            w.any = plane_alpha(ay, w.qy);
-        } else {
-            w.iz += az.step;
-            if ((unsigned)w.iz >= (unsigned)v.nz) break;
-            w.idx += sz;
-            w.qz += (float)az.step;
-            w.anz = plane_alpha(az, w.qz);
+    if (odd) {
+        // plane-by-plane walk over the whole ray from global memory
+        int ix = ordered_cell(ax, S[0], d[0], amin, 0, v.nx);
+        int iy = ordered_cell(ay, S[1], d[1], amin, 0, v.ny);
+        int iz = ordered_cell(az, S[2], d[2], amin, 0, v.nz);
+        float qx = (float)(ix + (ax.step > 0)), qy = (float)(iy + (ay.step > 0)), qz = (float)(iz + (az.step > 0));
+        float anx = plane_alpha(ax, qx), any = plane_alpha(ay, qy), anz = plane_alpha(az, qz);
+        float acur = amin;
+        for (int left = v.nx + v.ny + v.nz + 3; left > 0; --left) {
+            const float an = fminf(anx, fminf(any, anz));
+            const float ae = fminf(an, amax);
+            r.acc = __builtin_fmaf(fmaxf(ae - acur, 0.0f),
+                                   vol[(__umul24((unsigned)iz, (unsigned)v.ny) + (unsigned)iy) * (unsigned)v.nx +
+                                       (unsigned)ix],
+                                   r.acc);
+            if (an >= amax) break;
+            acur = an;
+            if (an == anx) {
+                ix += ax.step;
+                if ((unsigned)ix >= (unsigned)v.nx) break;
+                qx += (float)ax.step;
+                anx = plane_alpha(ax, qx);
+            } else if (an == any) {
+                iy += ay.step;
+                if ((unsigned)iy >= (unsigned)v.ny) break;
+                qy += (float)ay.step;
+                any = plane_alpha(ay, qy);
+            } else {
+                iz += az.step;
+                if ((unsigned)iz >= (unsigned)v.nz) break;
+                qz += (float)az.step;
+                anz = plane_alpha(az, qz);
+            }
         }
     }
-    if (active) proj[((int64_t)view * det.nv + iv) * det.nu + iu] = w.acc * L;
+    if (active) proj[((int64_t)view * det.nv + iv) * det.nu + iu] = r.acc * L;
 }
 
 // ------------------------------------------------------------ interpolated
@@ -585,9 +767,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_F
             const float ox = (float)b.o[0], oyf = (float)b.o[1], ozf = (float)b.o[2];
             const int oy = 4 * b.e[0], oz = 4 * b.e[0] * b.e[1];
             const char* base = reinterpret_cast<const char*>(box);
-            for (; k <= kl; ++k) {
+            // samples k..kl by their offset j = k - kc from the ray's anchor, an
+            // exact FP32 integer (interp_pos's position, without an int->float
+            // conversion per sample).  Only a ray with samples here enters: its
+            // offsets are below its sample count, far below 2^24, so the FP32
+            // counter steps exactly and the loop ends.
+            const float jl = (float)(kl - r.kc);
+            for (float j = (float)(k - r.kc); k <= kl && j <= jl; j += 1.0f) {
                 float p[3];
-                interp_pos(r, k, p);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) p[i] = __builtin_fmaf(j, r.st[i], r.base[i]);
                 const float fx = __builtin_floorf(p[0]), fy = __builtin_floorf(p[1]), fz = __builtin_floorf(p[2]);
                 const int off = (int)__builtin_fmaf(fz - ozf, SZ, __builtin_fmaf(fy - oyf, SY, (fx - ox) * 4.0f));
                 const float* r0 = reinterpret_cast<const float*>(base + off);
@@ -599,6 +788,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_F
                 const float c10 = lerp1(ax, r2[0], r2[1]), c11 = lerp1(ax, r3[0], r3[1]);
                 acc += lerp1(az, lerp1(ay, c00, c01), lerp1(ay, c10, c11));
             }
+            k = max(k, kl + 1);
         } else {
             for (; k <= kl; ++k) {
                 float p[3];

@@ -90,12 +90,18 @@ def data_range(geo, x_gt: np.ndarray) -> float:
     return float(vals.max() - vals.min())
 
 
-def make_pairs(plan: Plan, dense: Plan, vols, kind: str = "interp", ks=KS, dense_iters: int = 20):
+def make_pairs(plan: Plan, dense: Plan, vols, kind: str = "interp", ks=KS, dense_iters: int = 20, log=None,
+               log_every: int = 5):
     """(inputs, targets) on the device: sparse-view CGLS-k iterates and the
     dense-view CGLS reconstruction of the same phantom (`vols` may be any
-    iterable of host phantoms)."""
+    iterable of host phantoms).  With `log`, a progress line every
+    `log_every` phantoms (after the device has finished them)."""
     inputs, targets = [], []
-    for v in vols:
+    t0 = time.perf_counter()
+    for n, v in enumerate(vols):
+        if log is not None and n and n % log_every == 0:
+            torch.cuda.synchronize()
+            log(f"pairs of {n} phantoms in {time.perf_counter() - t0:.1f} s")
         xg = torch.from_numpy(v).to(plan.device)
         b = plan.forward(xg, kind=kind)
         _, h = algs.cgls(plan, b, max(ks), kind=kind, snapshots=ks, sync=False)
@@ -338,7 +344,8 @@ def main(argv=None):
         seeds = range(a.first_seed, a.first_seed + a.phantoms)
         dense = Plan(geo, synth.circular_angles(720))
         ks = tuple(int(k) for k in a.ks.split(","))
-        inputs, targets = make_pairs(plan, dense, phantom_stream("sparse256", seeds, a.workers), a.kind, ks=ks)
+        inputs, targets = make_pairs(plan, dense, phantom_stream("sparse256", seeds, a.workers), a.kind, ks=ks,
+                                     log=log)
         del dense
         torch.cuda.synchronize()
         nk = len(ks)
