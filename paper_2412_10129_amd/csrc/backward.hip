@@ -364,13 +364,39 @@ __device__ __forceinline__ void acc_add(u64* a, float q) { atomicAdd(a, to_fixed
 
 constexpr int SID_CELLS = CTMI_BWD_SID_CELLS;   // dominant-axis cells per Siddon item
 
+template <typename T>
+__device__ __forceinline__ T pick3(int i, T v0, T v1, T v2)
+{
+    return i == 0 ? v0 : (i == 1 ? v1 : v2);
+}
+
+__device__ __forceinline__ SiddonAxis pick_axis(int i, const SiddonAxis& x, const SiddonAxis& y, const SiddonAxis& z)
+{
+    SiddonAxis r;
+    r.inv = pick3(i, x.inv, y.inv, z.inv);
+    r.c = pick3(i, x.c, y.c, z.c);
+    r.step = pick3(i, x.step, y.step, z.step);
+    return r;
+}
+
+// An axis rebuilt from the (inv, c) that siddon_axis stored: inv has the
+// sign of d, and is 0 (with c = inf) for a ray parallel to the planes
+__device__ __forceinline__ SiddonAxis table_axis(float inv, float c)
+{
+    SiddonAxis r;
+    r.inv = inv;
+    r.c = c;
+    r.step = inv > 0.0f ? 1 : (inv < 0.0f ? -1 : 0);
+    return r;
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
                                                          const ViewGeo64* __restrict__ tab64, int view0, int nviews,
                                                          VolDims v, DetDims det, BrickMap m, float beta, float cmax)
 {
     __shared__ SAcc acc[NB];
-    __shared__ float t_S[3][256], t_d[3][256];
+    __shared__ float t_S[3][256], t_d[3][256], t_inv[3][256], t_cc[3][256];
     __shared__ float t_a0[256], t_a1[256], t_y[256];
     __shared__ int t_c0[256], t_nc[256], t_pre[256];
     __shared__ unsigned char imap[MAPCAP];
@@ -435,6 +461,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                             t_S[a][tid] = S[a];
                             t_d[a][tid] = d[a];
                         }
+                        t_inv[0][tid] = ax0.inv;
+                        t_inv[1][tid] = ax1.inv;
+                        t_inv[2][tid] = ax2.inv;
+                        t_cc[0][tid] = ax0.c;
+                        t_cc[1][tid] = ax1.c;
+                        t_cc[2][tid] = ax2.c;
                         t_a0[tid] = amin;
                         t_a1[tid] = amax;
                         t_c0[tid] = c0 * 4 + dom;
@@ -469,22 +501,81 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 const int q = it - t_pre[r];
                 const float S[3] = {t_S[0][r], t_S[1][r], t_S[2][r]};
                 const float d[3] = {t_d[0][r], t_d[1][r], t_d[2][r]};
-                const SiddonAxis ax = siddon_axis(S[0], d[0]);
-                const SiddonAxis ay = siddon_axis(S[1], d[1]);
-                const SiddonAxis az = siddon_axis(S[2], d[2]);
+                // the ray's axes as its table row computed them (siddon_axis)
+                const SiddonAxis ax = table_axis(t_inv[0][r], t_cc[0][r]);
+                const SiddonAxis ay = table_axis(t_inv[1][r], t_cc[1][r]);
+                const SiddonAxis az = table_axis(t_inv[2][r], t_cc[2][r]);
                 const int dom = t_c0[r] & 3, c0 = t_c0[r] >> 2;
-                SiddonAxis ad;
-                ad.inv = dom == 0 ? ax.inv : (dom == 1 ? ay.inv : az.inv);
-                ad.c = dom == 0 ? ax.c : (dom == 1 ? ay.c : az.c);
-                ad.step = dom == 0 ? ax.step : (dom == 1 ? ay.step : az.step);
+                const SiddonAxis ad = pick_axis(dom, ax, ay, az);
                 const int nc = t_nc[r];
                 const int cfirst = c0 + ad.step * q * SID_CELLS;
-                const int clast = c0 + ad.step * min(q * SID_CELLS + SID_CELLS - 1, nc - 1);
+                const int nl = min(SID_CELLS, nc - q * SID_CELLS);   // dominant-axis cells (layers) of the item
+                const int clast = cfirst + ad.step * (nl - 1);
                 // the item spans dominant-axis cells cfirst..clast; its ends are
-                // the planes the forward walk crosses there (same formula)
-                const float astart = q == 0 ? t_a0[r] : plane_alpha(ad, (float)(cfirst + (ad.step < 0)));
-                const float aend = (q * SID_CELLS + SID_CELLS >= nc) ? t_a1[r]
-                                                                     : plane_alpha(ad, (float)(clast + (ad.step > 0)));
+                // the planes the forward walk crosses there (same formula),
+                // kept inside the ray's stretch in the brick: where the ray
+                // leaves (or enters) through another face within a few ulps of
+                // such a plane, the FP32 plane parameter can fall past the
+                // stretch, and the walk must not cross that face
+                const float a0r = t_a0[r], a1r = t_a1[r];
+                const float astart = q == 0 ? a0r : fmaxf(plane_alpha(ad, (float)(cfirst + (ad.step < 0))), a0r);
+                const float aend = (q * SID_CELLS + SID_CELLS >= nc)
+                                       ? a1r
+                                       : fminf(plane_alpha(ad, (float)(clast + (ad.step > 0))), a1r);
+                const float yl = t_y[r];
+                // the two other axes (b, c) of the ray
+                const int b = dom == 0 ? 1 : 0, c = dom == 2 ? 1 : 2;
+                const float Db = pick3(b, d[0], d[1], d[2]), Dc = pick3(c, d[0], d[1], d[2]);
+                const float Dd = pick3(dom, d[0], d[1], d[2]);
+                if (fabsf(Db) <= 0.99f * fabsf(Dd) && fabsf(Dc) <= 0.99f * fabsf(Dd)) {
+                    // layer walk: within one dominant-axis cell the ray crosses at
+                    // most one plane of b and one of c (it runs below 0.99 along
+                    // both), so the cell's at most three segments follow from the
+                    // two next crossing parameters (the forward kernel's form)
+                    const SiddonAxis B = pick_axis(b, ax, ay, az), C = pick_axis(c, ax, ay, az);
+                    const int ib = ordered_cell(B, pick3(b, S[0], S[1], S[2]), Db, astart, pick3(b, x0, y0, z0),
+                                                pick3(b, x1, y1, z1));
+                    const int ic = ordered_cell(C, pick3(c, S[0], S[1], S[2]), Dc, astart, pick3(c, x0, y0, z0),
+                                                pick3(c, x1, y1, z1));
+                    float qb = (float)(ib + (B.step > 0)), qc = (float)(ic + (C.step > 0));
+                    // a parallel axis has inv = 0 and c = inf: its crossings stay at inf
+                    float anb = __builtin_fmaf(qb, B.inv, B.c), anc = __builtin_fmaf(qc, C.inv, C.c);
+                    const int ix = dom == 0 ? cfirst : (b == 0 ? ib : ic);
+                    const int iy = dom == 1 ? cfirst : (dom == 0 ? ib : ic);
+                    const int iz = dom == 2 ? cfirst : ic;
+                    // cell offsets in bytes of the accumulator array
+                    constexpr int E = (int)sizeof(SAcc);
+                    int li = E * (int)(__umul24(__umul24(iz - z0, BY) + (iy - y0), BX) + (ix - x0));
+                    const int SD = E * ad.step * pick3(dom, 1, BX, BX * BY);
+                    const int DB = E * B.step * pick3(b, 1, BX, BX * BY), DC = E * C.step * pick3(c, 1, BX, BX * BY);
+                    char* accb = (char*)acc;
+                    float qa = (float)(cfirst + (ad.step > 0));   // exit plane of the current layer
+                    const float fa = (float)ad.step, fb = (float)B.step, fc = (float)C.step;
+                    // (an empty stretch, astart past aend by rounding, adds nothing)
+                    float acur = fminf(astart, aend);
+                    asm volatile("" ::"v"(yl), "v"(acur), "v"(aend), "v"(li));
+                    for (int l = 0; l < nl; ++l) {
+                        const float ae = __builtin_amdgcn_fmed3f(__builtin_fmaf(qa, ad.inv, ad.c), acur, aend);
+                        const bool cb = anb < ae, cc = anc < ae, bfirst = anb <= anc;
+                        const float t1 = __builtin_amdgcn_fmed3f(bfirst ? anb : anc, acur, ae);
+                        const float t2 = __builtin_amdgcn_fmed3f(bfirst ? anc : anb, acur, ae);
+                        const int db = cb ? DB : 0, dc = cc ? DC : 0;
+                        const float s1 = t2 - t1, s2 = ae - t2;
+                        acc_add((SAcc*)(accb + li), (t1 - acur) * yl);
+                        if (s1 > 0.0f) acc_add((SAcc*)(accb + li + (bfirst ? db : dc)), s1 * yl);
+                        if (s2 > 0.0f) acc_add((SAcc*)(accb + li + db + dc), s2 * yl);
+                        acur = ae;
+                        li += db + dc + SD;
+                        qa += fa;
+                        qb = cb ? qb + fb : qb;
+                        qc = cc ? qc + fc : qc;
+                        anb = __builtin_fmaf(qb, B.inv, B.c);
+                        anc = __builtin_fmaf(qc, C.inv, C.c);
+                    }
+                    continue;
+                }
+                // a ray as steep along b or c as along its dominant axis (to 1 %)
+                // may cross two planes of one axis in a layer: plane-by-plane walk
                 int ix = ordered_cell(ax, S[0], d[0], astart, x0, x1);
                 int iy = ordered_cell(ay, S[1], d[1], astart, y0, y1);
                 int iz = ordered_cell(az, S[2], d[2], astart, z0, z1);
@@ -495,7 +586,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 float anx = plane_alpha(ax, qx), any = plane_alpha(ay, qy), anz = plane_alpha(az, qz);
                 int li = __umul24(__umul24(iz - z0, BY) + (iy - y0), BX) + (ix - x0);
                 const int sx = ax.step, sy = ay.step * BX, sz = az.step * BX * BY;
-                const float yl = t_y[r];
                 float acur = astart;
                 const float fx = (float)ax.step, fy = (float)ay.step, fz = (float)az.step;
                 asm volatile("" ::"v"(yl), "v"(acur), "v"(aend), "v"(li));
