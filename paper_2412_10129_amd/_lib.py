@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libctmi.so")
+# the in-tree build; CTMI_LIB names another build of the same library (for
+# instance one compiled with other tile or slab sizes)
+LIB_PATH = os.environ.get("CTMI_LIB") or os.path.join(HERE, "libctmi.so")
 
 CTMI_OK, CTMI_EINVAL, CTMI_EUNSUPPORTED, CTMI_EOVERFLOW, CTMI_EWORKSPACE, CTMI_EHIP = 0, -1, -2, -3, -4, -5
 CTMI_SIDDON, CTMI_INTERP = 0, 1

@@ -189,10 +189,10 @@ def evaluate(plan: Plan, net: UNet, vols, niter: int = 60, every: int = 5, ratio
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_sparse256.pt")
 
 
-def save_weights(net: UNet, path: str, meta: Dict) -> None:
-    """The trained network's FP32 parameters (no optimiser state) with a
+def save_weights(params: torch.Tensor, path: str, meta: Dict) -> None:
+    """A trained network's FP32 parameters (no optimiser state) with a
     description of its training."""
-    torch.save({"params": net.params.detach().cpu(), "meta": json.dumps(meta)}, path)
+    torch.save({"params": params.detach().cpu().contiguous(), "meta": json.dumps(meta)}, path)
 
 
 def load_weights(net: UNet, path: str) -> Dict:
@@ -325,16 +325,15 @@ def main(argv=None):
         bench_unet(a.repeat, log)
         return
     if a.cmd == "export":
-        net = UNet(seed=0)
+        # a checkpoint holds the FP32 master parameters with the Adam state;
+        # the weights file keeps the parameters only (no GPU needed)
         sd = torch.load(a.ckpt, map_location="cpu", weights_only=True)
-        net.load_state_dict({k: (v.to(net.device) if k != "t" else v) for k, v in sd.items()
-                             if k in ("params", "m", "v", "t")})
         seen = sorted(int(v) for v in sd.get("phantoms", torch.zeros(0, dtype=torch.int64)).tolist())
         meta = {"pairs": a.pairs, "phantom_seeds": [seen[0], seen[-1]] if seen else None, "phantoms": len(seen),
-                "input_iterations": a.ks, "target": "CGLS-20 on 720 views", "adam_steps": int(net.t),
+                "input_iterations": a.ks, "target": "CGLS-20 on 720 views", "adam_steps": int(sd["t"]),
                 "crop": 64, "batch": 4}
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
-        save_weights(net, a.out, meta)
+        save_weights(sd["params"], a.out, meta)
         log(json.dumps(meta))
         return
     geo, ang = synth.workload("sparse256")
