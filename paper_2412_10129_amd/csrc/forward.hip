@@ -52,8 +52,13 @@ namespace {
 #define CTMI_FWD_WAVES 6
 #endif
 constexpr int TU = CTMI_FWD_TU, TV = CTMI_FWD_TV;   // ray tile (pixels), TU * TV = 256
-constexpr int SLAB = CTMI_FWD_SLAB;                 // slab thickness along the dominant axis
+#ifndef CTMI_FWD_SID_SLAB
+#define CTMI_FWD_SID_SLAB 12
+#endif
+constexpr int SLAB = CTMI_FWD_SLAB;                 // slab thickness along the dominant axis (interpolated)
+constexpr int SID_SLAB = CTMI_FWD_SID_SLAB;         // the same for the Siddon layer walk
 constexpr int BOXCAP = CTMI_FWD_BOXCAP;             // LDS floats for the staged box
+constexpr int SLABTAB = 64;                         // slab boxes formed up front per block
 static_assert(TU * TV == 256, "one ray per thread");
 static_assert(BOXCAP < 65536, "box index must stay below 2^16");
 
@@ -412,6 +417,7 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
                                                         VolDims v, DetDims det)
 {
     __shared__ float box[BOXCAP];
+    __shared__ int sbox[SLABTAB][7];   // the first SLABTAB slabs' boxes (origin, extent, non-empty)
     int view, tu0, tv0;
     tile_of_block(m, blockIdx.x, view, tu0, tv0);
     const int iu = tu0 + (int)(threadIdx.x % TU), iv = tv0 + (int)(threadIdx.x / TU);
@@ -475,27 +481,60 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
     khi = __builtin_amdgcn_readfirstlane(khi);
     const bool wave_steep = __any(steep);
 
-    const int nslab = (na + SLAB - 1) / SLAB;
+    const int nslab = (na + SID_SLAB - 1) / SID_SLAB;
     const int clo[3] = {0, 0, 0}, chi[3] = {v.nx - 1, v.ny - 1, v.nz - 1};
-
-    for (int si = 0; si < nslab; ++si) {
+    // the staged box of slab si (in the direction of travel): the cells
+    // under the bundle, no margin (a ray whose walk rounds into a cell
+    // outside, a corner ray within ulps of a plane, finds out below and
+    // reads that slab plane by plane)
+    auto slab_box = [&](int si, Box& bx) -> bool {
         const int s = dir > 0 ? si : nslab - 1 - si;
-        const int c0 = s * SLAB, c1 = min(c0 + SLAB, na);   // cells [c0, c1) along a
+        const int c0 = s * SID_SLAB, c1 = min(c0 + SID_SLAB, na);   // cells [c0, c1) along a
         float blo[3], bhi[3];
         bundle_bounds(g, det, tu0, tv0, a, (float)c0, (float)c1, 0.0f, blo, bhi);
         int lo[3], hi[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            lo[i] = (int)__builtin_floorf(fmaxf(blo[i], -4.0f)) - 1;
-            hi[i] = (int)__builtin_floorf(fminf(bhi[i], 1.0e7f)) + 1;
+            lo[i] = (int)__builtin_floorf(fmaxf(blo[i], -4.0f));
+            hi[i] = (int)__builtin_floorf(fminf(bhi[i], 1.0e7f));
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             lo[i] = i == a ? c0 : lo[i];
             hi[i] = i == a ? c1 - 1 : hi[i];
         }
+        return make_box(lo, hi, clo, chi, a, bx);
+    };
+    // the first SLABTAB boxes are formed once, one slab per thread, instead
+    // of by every wave at every slab
+    if ((int)threadIdx.x < min(nslab, SLABTAB)) {
         Box bx;
-        if (!make_box(lo, hi, clo, chi, a, bx)) continue;
+        const bool ok = slab_box((int)threadIdx.x, bx);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sbox[threadIdx.x][i] = bx.o[i];
+            sbox[threadIdx.x][3 + i] = bx.e[i];
+        }
+        sbox[threadIdx.x][6] = ok ? 1 : 0;
+    }
+    __syncthreads();
+
+    for (int si = 0; si < nslab; ++si) {
+        const int s = dir > 0 ? si : nslab - 1 - si;
+        const int c0 = s * SID_SLAB, c1 = min(c0 + SID_SLAB, na);   // cells [c0, c1) along a
+        Box bx;
+        bool ok;
+        if (si < SLABTAB) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                bx.o[i] = sbox[si][i];
+                bx.e[i] = sbox[si][3 + i];
+            }
+            ok = sbox[si][6] != 0;
+        } else {
+            ok = slab_box(si, bx);
+        }
+        if (!ok) continue;
         // the box is the same in every lane: scalar registers
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -515,9 +554,11 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
         const int oa = pick3(a, bx.o[0], bx.o[1], bx.o[2]);
         const int ob = pick3(b, bx.o[0], bx.o[1], bx.o[2]), eb = pick3(b, bx.e[0], bx.e[1], bx.e[2]);
         const int oc = pick3(c, bx.o[0], bx.o[1], bx.o[2]), ec = pick3(c, bx.e[0], bx.e[1], bx.e[2]);
-        // does this ray's path through the slab stay inside the box?  (the
-        // cells at both ends of its clipped stretch, one cell of margin; a
-        // ray with no stretch here sits the slab out)
+        // does this ray's path through the slab stay inside the box?  Its
+        // cells along b (and c) run monotonically from its current one to
+        // the one it holds at the end of its stretch here, which
+        // ordered_cell gives in the walk's crossing order; a ray with no
+        // stretch here sits the slab out
         bool inbox = true, idle = true;
         int roff = 0;   // byte offset of the ray's (b, c) cell in a layer of the box
         {
@@ -526,14 +567,8 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
             const int ib = (int)r.qb - (B.step > 0), ic = (int)r.qc - (C.step > 0);
             if (t0 < t1) {
                 idle = false;
-                const float pb0 = __builtin_fmaf(t0, Db, Sb), pb1 = __builtin_fmaf(t1, Db, Sb);
-                const float pc0 = __builtin_fmaf(t0, Dc, Sc), pc1 = __builtin_fmaf(t1, Dc, Sc);
-                const int bl = max((int)__builtin_floorf(fminf(pb0, pb1)) - 1, 0);
-                const int bh = min((int)__builtin_floorf(fmaxf(pb0, pb1)) + 1, nb - 1);
-                const int cl = max((int)__builtin_floorf(fminf(pc0, pc1)) - 1, 0);
-                const int ch = min((int)__builtin_floorf(fmaxf(pc0, pc1)) + 1, nc - 1);
-                inbox = bl >= ob && bh < ob + eb && cl >= oc && ch < oc + ec && ib >= bl && ib <= bh &&
-                        ic >= cl && ic <= ch;
+                const int ibe = ordered_cell(B, Sb, Db, t1, 0, nb), ice = ordered_cell(C, Sc, Dc, t1, 0, nc);
+                inbox = min(ib, ibe) >= ob && max(ib, ibe) < ob + eb && min(ic, ice) >= oc && max(ic, ice) < oc + ec;
                 roff = inbox ? 4 * ((ib - ob) * st_b + (ic - oc) * st_c) : 0;
             }
         }
@@ -646,6 +681,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_F
 {
     __shared__ float box[BOXCAP];
     __shared__ Bundle bun;
+    __shared__ int sbox[SLABTAB][7];   // the first SLABTAB slabs' boxes (origin, extent, fits | clipped << 1)
     int view, tu0, tv0;
     tile_of_block(m, blockIdx.x, view, tu0, tv0);
     const int iu = tu0 + (int)(threadIdx.x % TU), iv = tv0 + (int)(threadIdx.x / TU);
@@ -731,13 +767,45 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_F
             for (int i = 0; i < 3; ++i) clipped |= b.o[i] > max(lo[i], clo[i]) || b.o[i] + b.e[i] - 1 < min(hi[i], chi[i]);
         }
     };
+    // the first SLABTAB boxes are formed once, one slab per thread, instead
+    // of by every wave at every slab
+    if ((int)threadIdx.x < min(nslab, SLABTAB)) {
+        int A0, A1;
+        Box bx;
+        bool fits, clipped;
+        slab_box((int)threadIdx.x, A0, A1, bx, fits, clipped);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sbox[threadIdx.x][i] = bx.o[i];
+            sbox[threadIdx.x][3 + i] = bx.e[i];
+        }
+        sbox[threadIdx.x][6] = (fits ? 1 : 0) | (clipped ? 2 : 0);
+    }
+    __syncthreads();
+    auto slab_of = [&](int si, int& A0, int& A1, Box& b, bool& fits, bool& clipped) {
+        if (si < SLABTAB) {
+            const int s = dir > 0 ? si : nslab - 1 - si;
+            A0 = s * SLAB - 1;
+            A1 = A0 + SLAB;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                b.o[i] = __builtin_amdgcn_readfirstlane(sbox[si][i]);
+                b.e[i] = __builtin_amdgcn_readfirstlane(sbox[si][3 + i]);
+            }
+            const int f = __builtin_amdgcn_readfirstlane(sbox[si][6]);
+            fits = (f & 1) != 0;
+            clipped = (f & 2) != 0;
+        } else {
+            slab_box(si, A0, A1, b, fits, clipped);
+        }
+    };
     // the next slab's box is fetched into registers while this one is sampled
     constexpr int PF = CTMI_FWD_PF;
     float pf[PF];
     int nA0, nA1;
     Box nb;
     bool nfits, nclipped;
-    slab_box(0, nA0, nA1, nb, nfits, nclipped);
+    slab_of(0, nA0, nA1, nb, nfits, nclipped);
     fetch_box<PF>(pf, vol, v, nb, nfits);
 
     for (int si = 0; si < nslab; ++si) {
@@ -756,7 +824,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_F
         put_box<PF>(box, pf, vol, v, b, fits);
         __syncthreads();
         if (si + 1 < nslab) {
-            slab_box(si + 1, nA0, nA1, nb, nfits, nclipped);
+            slab_of(si + 1, nA0, nA1, nb, nfits, nclipped);
             fetch_box<PF>(pf, vol, v, nb, nfits);
         }
         if (fits && !clipped && mono) {
