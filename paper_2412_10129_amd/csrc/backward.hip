@@ -40,7 +40,7 @@ namespace ctmi {
 namespace {
 
 #ifndef CTMI_BWD_SID_CELLS
-#define CTMI_BWD_SID_CELLS 4
+#define CTMI_BWD_SID_CELLS 16
 #endif
 #ifndef CTMI_BWD_INT_SAMPLES
 #define CTMI_BWD_INT_SAMPLES 6

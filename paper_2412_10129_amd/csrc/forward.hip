@@ -51,6 +51,10 @@ namespace {
 #ifndef CTMI_FWD_WAVES
 #define CTMI_FWD_WAVES 6
 #endif
+// Siddon forward: waves per SIMD the register budget is sized for
+#ifndef CTMI_FWD_SID_WAVES
+#define CTMI_FWD_SID_WAVES 6
+#endif
 constexpr int TU = CTMI_FWD_TU, TV = CTMI_FWD_TV;   // ray tile (pixels), TU * TV = 256
 #ifndef CTMI_FWD_SID_SLAB
 #define CTMI_FWD_SID_SLAB 12
@@ -244,10 +248,12 @@ __device__ __forceinline__ Stage stage_of(const Box& b, const VolDims& v)
 }
 
 // value of the current element (0 outside the volume), then advance a pass
+template <bool CHECK>
 __device__ __forceinline__ float stage_next(Stage& s, const float* __restrict__ vol, const VolDims& v, const Box& b)
 {
     float val = 0.0f;
-    if (s.xok && (unsigned)(b.o[1] + s.ly) < (unsigned)v.ny && (unsigned)(b.o[2] + s.lz) < (unsigned)v.nz)
+    // (CHECK false: the caller knows the box lies inside the volume)
+    if (!CHECK || (s.xok && (unsigned)(b.o[1] + s.ly) < (unsigned)v.ny && (unsigned)(b.o[2] + s.lz) < (unsigned)v.nz))
         val = vol[s.gi];
     s.ly += s.rgy;
     const bool c = s.ly >= b.e[1];
@@ -273,6 +279,7 @@ __device__ __forceinline__ float element_value(const float* __restrict__ vol, co
     return val;
 }
 
+template <bool CHECK = true>
 __device__ __forceinline__ void load_box(float* box, const float* __restrict__ vol, const VolDims& v, const Box& b)
 {
     if (b.e[0] > 256) {
@@ -281,10 +288,18 @@ __device__ __forceinline__ void load_box(float* box, const float* __restrict__ v
         return;
     }
     Stage s = stage_of(b, v);
+    if (!CHECK) s.xok = true;
     while (s.lz < b.e[2]) {
         const int li = s.li;
-        box[li] = stage_next(s, vol, v, b);
+        box[li] = stage_next<CHECK>(s, vol, v, b);
     }
+}
+
+// the box lies inside the volume (no staged cell needs a bounds check)
+__device__ __forceinline__ bool box_inside(const Box& b, const VolDims& v)
+{
+    return b.o[0] >= 0 && b.o[1] >= 0 && b.o[2] >= 0 && b.o[0] + b.e[0] <= v.nx && b.o[1] + b.e[1] <= v.ny &&
+           b.o[2] + b.e[2] <= v.nz;
 }
 
 // Software-pipelined staging: the first PF passes of the next slab's box
@@ -296,11 +311,20 @@ __device__ __forceinline__ void fetch_box(float (&r)[PF], const float* __restric
 {
     if (on && b.e[0] <= 256) {
         Stage s = stage_of(b, v);
+        if (box_inside(b, v)) {
 #pragma unroll
-        for (int m = 0; m < PF; ++m) {
-            const bool row = s.lz < b.e[2];
-            const float val = stage_next(s, vol, v, b);
-            r[m] = row ? val : 0.0f;
+            for (int m = 0; m < PF; ++m) {
+                const bool row = s.lz < b.e[2];
+                const float val = row ? stage_next<false>(s, vol, v, b) : 0.0f;
+                r[m] = val;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < PF; ++m) {
+                const bool row = s.lz < b.e[2];
+                const float val = stage_next<true>(s, vol, v, b);
+                r[m] = row ? val : 0.0f;
+            }
         }
     } else {
 #pragma unroll
@@ -328,9 +352,16 @@ __device__ __forceinline__ void put_box(float* box, const float (&r)[PF], const 
         s.gi += s.d1 + (c ? s.d2 : 0u);
         s.li += s.lstep;
     }
-    while (s.lz < b.e[2]) {
-        const int li = s.li;
-        box[li] = stage_next(s, vol, v, b);
+    if (box_inside(b, v)) {
+        while (s.lz < b.e[2]) {
+            const int li = s.li;
+            box[li] = stage_next<false>(s, vol, v, b);
+        }
+    } else {
+        while (s.lz < b.e[2]) {
+            const int li = s.li;
+            box[li] = stage_next<true>(s, vol, v, b);
+        }
     }
 }
 
@@ -411,7 +442,7 @@ __device__ __forceinline__ void walk_layer(LayerRay& r, float ae, int k, int a, 
     r.acur = ae;
 }
 
-__global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict__ vol, float* __restrict__ proj,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_FWD_SID_WAVES, 8))) k_forward_siddon(const float* __restrict__ vol, float* __restrict__ proj,
                                                         const ViewGeo* __restrict__ tab,
                                                         const ViewGeo64* __restrict__ tab64, int view0, TileMap m,
                                                         VolDims v, DetDims det)
@@ -542,7 +573,7 @@ __global__ void __launch_bounds__(256) k_forward_siddon(const float* __restrict_
             bx.e[i] = __builtin_amdgcn_readfirstlane(bx.e[i]);
         }
         __syncthreads();
-        load_box(box, vol, v, bx);
+        load_box<false>(box, vol, v, bx);   // (clipped to the volume by make_box)
         __syncthreads();
         const int k0 = max(c0, klo), k1 = min(c1 - 1, khi);
         if (k0 > k1) continue;   // no ray of this wave reaches these layers
