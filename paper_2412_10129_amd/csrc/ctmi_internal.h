@@ -253,7 +253,9 @@ __device__ __forceinline__ SiddonAxis siddon_axis(float S, float d)
 {
     SiddonAxis ax;
     if (d != 0.0f) {
-        ax.inv = 1.0f / d;
+        // the hardware reciprocal (1 ulp): every kernel forms its crossing
+        // parameters from this same value
+        ax.inv = __builtin_amdgcn_rcpf(d);
         ax.c = -S * ax.inv;
         ax.step = d > 0.0f ? 1 : -1;
     } else {

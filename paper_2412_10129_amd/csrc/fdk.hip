@@ -213,11 +213,20 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
-__device__ __forceinline__ float row_weight(const FilterArgs& fa, int iu, int iv)
+// Detector row iv's constant in the cosine weight: DSD^2 + v^2.
+__device__ __forceinline__ float row_const(const FilterArgs& fa, int iv)
+{
+    const float v = __builtin_fmaf((float)iv + 0.5f - 0.5f * (float)fa.nv, fa.dv, fa.ov);
+    return __builtin_fmaf(fa.DSD, fa.DSD, v * v);
+}
+
+// Pre-weight of pixel (iu, row with constant cv): DSD / sqrt(DSD^2 + u^2 +
+// v^2) with the hardware reciprocal square root (1 ulp), times Wang's
+// offset-detector weight when asked for.
+__device__ __forceinline__ float row_weight(const FilterArgs& fa, int iu, float cv)
 {
     const float u = __builtin_fmaf((float)iu + 0.5f - 0.5f * (float)fa.nu, fa.du, fa.ou);
-    const float v = __builtin_fmaf((float)iv + 0.5f - 0.5f * (float)fa.nv, fa.dv, fa.ov);
-    float w = fa.DSD / __builtin_sqrtf(__builtin_fmaf(fa.DSD, fa.DSD, __builtin_fmaf(u, u, v * v)));
+    float w = fa.DSD * __builtin_amdgcn_rsqf(__builtin_fmaf(u, u, cv));
     if (fa.wang) {
         const float up = u * fa.wang_sign;
         float ww;
@@ -418,11 +427,12 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
         float* oa = out + r0 * fa.nu;
         float* ob = out + r1 * fa.nu;
         // weighted rows, zero beyond nu (the linear convolution's padding)
+        const float cv0 = row_const(fa, iv0), cv1 = row_const(fa, iv1);
         auto src = [&](int n) {
             float x = 0.0f, y = 0.0f;
             if (n < fa.nu) {
-                x = a[n] * row_weight(fa, n, iv0);
-                if (has1) y = bb[n] * row_weight(fa, n, iv1);
+                x = a[n] * row_weight(fa, n, cv0);
+                if (has1) y = bb[n] * row_weight(fa, n, cv1);
             }
             return make_float2(x, y);
         };
