@@ -108,8 +108,8 @@ def test_gradcheck_tiny(P, kind):
 @pytest.mark.parametrize("kind", ["siddon", "interp"])
 def test_gradient_vs_oracle_at_512(P, orc, kind):
     """512^3 x 720 views, 1024 x 768 detector: the autograd gradient of
-    |Ax - y|^2 on 12 sampled FOV voxels against the oracle's entry-by-entry
-    FP64 gradient."""
+    |Ax - y|^2 on 48 sampled FOV voxels (16 of them on the adjoint's brick
+    faces) against the oracle's entry-by-entry FP64 gradient."""
     geo, ang = synth.workload("cbct512")
     xh = synth.uniform_volume(geo, 66)
     yh = synth.uniform_projections(geo, len(ang), 67) * 200.0
@@ -121,9 +121,14 @@ def test_gradient_vs_oracle_at_512(P, orc, kind):
     torch.cuda.synchronize()
     rng = np.random.Generator(np.random.PCG64(68))
     nz, ny, nx = geo.nVoxel
-    iz = rng.integers(8, nz - 8, 12)
-    iy = rng.integers(96, ny - 96, 12)
-    ix = rng.integers(96, nx - 96, 12)
+    iz = rng.integers(8, nz - 8, 32)
+    iy = rng.integers(96, ny - 96, 32)
+    ix = rng.integers(96, nx - 96, 32)
+    # voxels on 16x16x8 brick faces (x or y = 0 or 15 mod 16, z = 0 or 7 mod 8)
+    fz = rng.integers(1, nz // 8 - 1, 16) * 8 + rng.choice([0, 7], 16)
+    fy = rng.integers(6, ny // 16 - 6, 16) * 16 + rng.choice([0, 15], 16)
+    fx = rng.integers(6, nx // 16 - 6, 16) * 16 + rng.choice([0, 15], 16)
+    iz, iy, ix = np.concatenate([iz, fz]), np.concatenate([iy, fy]), np.concatenate([ix, fx])
     got = x.grad[torch.from_numpy(iz).cuda(), torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()]
     got = got.double().cpu().numpy()
     want = orc.gradient_voxels(geo, ang, xh, yh, iz, iy, ix, kind)
