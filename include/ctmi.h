@@ -54,7 +54,7 @@ extern "C" {
 enum {
     CTMI_OK = 0,
     CTMI_EINVAL = -1,       /* bad geometry, pointer, range or size */
-    CTMI_EUNSUPPORTED = -2, /* a geometry feature this build does not model */
+    CTMI_EUNSUPPORTED = -2, /* a geometry feature the library does not model */
     CTMI_EOVERFLOW = -3,    /* sizes beyond the library's index range */
     CTMI_EWORKSPACE = -4,   /* workspace missing or too small */
     CTMI_EHIP = -5          /* the HIP runtime reported an error */

@@ -309,7 +309,7 @@ def cgls(geo: Geometry, angles, b, niter: int, kind: str = "interp", x_gt=None, 
 def pnp_cgls(geo: Geometry, angles, b, niter: int, denoiser, every: int = 5, ratio: float = 1.05,
              kind: str = "interp", x_gt=None, mask=None):
     """CGLS with a plug-and-play denoiser (the learned prior used inside the
-    paper's Krylov solvers, section 2.2.1; the combination is this build's).
+    paper's Krylov solvers, section 2.2.1; the combination is ours).
 
     Runs CGLS from x = 0.  After every `every` iterations it proposes
     x' = denoiser(x) and computes r' = b - A x'.  The proposal is accepted

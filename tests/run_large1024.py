@@ -20,7 +20,7 @@ Input: the textured random-ellipsoid phantom (seed 7) voxelised on a 256^3
 grid of 1 mm voxels covering the same 256 mm cube, each voxel repeated 4x
 along every axis (a piecewise-constant 1024^3 phantom, 4 GB).
 
-    python tests/run_large1024.py --out gpurun_out/large1024.json
+    python tests/run_large1024.py --out large1024.json
 """
 from __future__ import annotations
 

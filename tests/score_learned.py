@@ -12,7 +12,7 @@ first iterate the oracle puts at or above the level, with the one before it
 below.  Levels: 40 dB, and plain CGLS's best PSNR (oracle value of its best
 iterate).  Times are the solver's GPU-event times summed up to the crossing.
 
-    python tests/judge_learned.py --ckpt CKPT --phantoms 20 --out result.json
+    python tests/score_learned.py --ckpt CKPT --phantoms 20 --out result.json
 """
 from __future__ import annotations
 
@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def crossing(level, dev_psnr, judge):
+def crossing(level, dev_psnr, score):
     """First iterate index whose oracle PSNR is >= level (None if none):
     starts from the device's proposal and walks until the oracle agrees
     that the iterate before is below the level."""
@@ -37,11 +37,11 @@ def crossing(level, dev_psnr, judge):
     if len(idx) == 0:
         return None
     k = int(idx[0])
-    while k < len(dev) and judge(k) < level:
+    while k < len(dev) and score(k) < level:
         k += 1
     if k == len(dev):
         return None
-    while k > 0 and judge(k - 1) >= level:
+    while k > 0 and score(k - 1) >= level:
         k -= 1
     return k
 
@@ -78,22 +78,22 @@ def main(argv=None):
     def on_run(n, x_gt, res, its):
         cache = {}
 
-        def judge_fn(name):
-            def judge(k):
+        def score_fn(name):
+            def score(k):
                 if (name, k) not in cache:
                     cache[(name, k)] = oracle.psnr(its[name][k].cpu().numpy(), x_gt, mask)
                 return cache[(name, k)]
-            return judge
+            return score
         rec = {"seed": a.first_seed + n}
-        jc, jp = judge_fn("cgls"), judge_fn("pnp")
+        jc, jp = score_fn("cgls"), score_fn("pnp")
         kbest = int(np.argmax(res["cgls"]["psnr"]))
         best = jc(kbest)
         rec["cgls_best_db_oracle"] = best
         rec["cgls_best_iter"] = kbest + 1
-        for name, judge in (("cgls", jc), ("pnp", jp)):
+        for name, score in (("cgls", jc), ("pnp", jp)):
             ms = np.cumsum(res[name]["ms"])
-            k40 = crossing(40.0, res[name]["psnr"], judge)
-            kb = crossing(best, res[name]["psnr"], judge)
+            k40 = crossing(40.0, res[name]["psnr"], score)
+            kb = crossing(best, res[name]["psnr"], score)
             rec[name] = {"iters_to_40db": None if k40 is None else k40 + 1,
                          "ms_to_40db": None if k40 is None else float(ms[k40]),
                          "iters_to_cgls_best": None if kb is None else kb + 1,
