@@ -229,6 +229,9 @@ def test_1024_backward_view_ranges_and_oracle_subset(P, orc, large, kind):
     geo, ang, plan = large["geo"], large["ang"], large["plan"]
     g = torch.Generator(device="cuda").manual_seed(77)
     y = torch.rand((len(ang),) + geo.nDetector, generator=g, device="cuda")
+    # the views the oracle sees come from the seeded host generator
+    tail_h = synth.uniform_projections(geo, 8, 76)
+    y[-8:] = torch.from_numpy(tail_h).cuda()
     full = plan.backproject(y, kind=kind)
     part = plan.backproject(y[:1000], kind=kind, view0=0, nviews=1000)
     plan.backproject(y[1000:], out=part, kind=kind, beta=1.0, view0=1000, nviews=len(ang) - 1000)
@@ -238,7 +241,7 @@ def test_1024_backward_view_ranges_and_oracle_subset(P, orc, large, kind):
     sub = plan.backproject(tail, kind=kind, view0=len(ang) - 8, nviews=8)
     iz, iy, ix = _fov_voxels(geo, 12, 78)
     got = sub[torch.from_numpy(iz).cuda(), torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()]
-    want = orc.adjoint_voxels(geo, ang[-8:], tail.double().cpu().numpy(), iz, iy, ix, kind)
+    want = orc.adjoint_voxels(geo, ang[-8:], tail_h.astype(np.float64), iz, iy, ix, kind)
     assert _rel(got.double().cpu().numpy(), want) < 1e-4
 
 
@@ -263,7 +266,10 @@ def test_1024_fdk_filter_wang_offset_detector(P, orc, large):
     geo, ang, plan = large["geo"], large["ang"], large["plan"]
     g = torch.Generator(device="cuda").manual_seed(80)
     y = torch.rand((len(ang),) + geo.nDetector, generator=g, device="cuda")
-    ref_in = y[:2].double().cpu().numpy()
+    # the rows the oracle filters come from the seeded host generator
+    ref_h = synth.uniform_projections(geo, 2, 81)
+    y[:2] = torch.from_numpy(ref_h).cuda()
+    ref_in = ref_h.astype(np.float64)
     plan.fdk_filter(y, out=y, wang=True)
     want = orc.fdk_filter(geo, ref_in, ntotal=len(ang), wang=True)
     assert _rel(y[:2].cpu().numpy(), want) < 1e-5
