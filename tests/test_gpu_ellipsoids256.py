@@ -8,11 +8,14 @@ Parity bar: rel-L2 1e-3 after 20 CGLS iterations (and after 20 OS-SART
 passes of 20 blocks of 18 views, nonneg), over 4096 seeded voxels and the
 central z and y slices; the per-iteration residual norms within 1e-3.
 
-Data: the GPU's own b = A x of the same FP32-rounded phantom, given the
-Poisson noise of the same seed on the host.  Its clean rays match the
-oracle's to FP32 rounding (checked); where that rounding moves a count
-across an integer the noisy values differ (a few rays in a thousand, each
-by one count), which moves the solution far less than the bar."""
+Data: the oracle's own b, remade here exactly as the golden writer made it
+(FP64 interpolated A x of the FP32-rounded phantom, then the seeded Poisson
+counts on the whole array), so both solvers start from the same numbers.
+Poisson sampling draws a variable number of uniforms per count, so counts
+drawn from projections that differ in the last bits (the GPU's FP32 A x)
+would follow a different random stream; the GPU's A x is checked against
+the oracle's at the sampled rays instead.  The oracle's A x takes about
+30 core-minutes (a progress line per 45 views)."""
 import json
 import os
 
@@ -43,7 +46,7 @@ def P():
 
 
 @pytest.fixture(scope="module")
-def work(P):
+def work(P, orc):
     have = {a: np.load(p, allow_pickle=False) for a, p in GOLD.items() if os.path.exists(p)}
     if not have:
         pytest.skip("golden results not written yet")
@@ -51,16 +54,22 @@ def work(P):
     meta = json.loads(str(g["meta"]))
     geo, ang = synth.workload("ellipsoids256")
     x_gt = synth.voxelize(geo, synth.random_ellipsoids(geo, meta["phantom_seed"]), dtype=np.float32)
-    plan = P.Plan(geo, ang)
-    b_clean = plan.forward(torch.from_numpy(x_gt).cuda(), kind="interp")
     rays = g["rays"]
-    got = b_clean[torch.from_numpy(rays[0]).cuda(), torch.from_numpy(rays[1]).cuda(), torch.from_numpy(rays[2]).cuda()]
+    plan = P.Plan(geo, ang)
+    b_gpu = plan.forward(torch.from_numpy(x_gt).cuda(), kind="interp")
+    got = b_gpu[torch.from_numpy(rays[0]).cuda(), torch.from_numpy(rays[1]).cuda(), torch.from_numpy(rays[2]).cuda()]
     assert _rel(got.double().cpu().numpy(), g["b_clean_rays"]) < 1e-5
-    b = synth.poisson_log_data(b_clean.cpu().numpy().astype(np.float64), meta["noise_seed"], I0=meta["I0"])
+    del b_gpu
+    parts = []
+    for v0 in range(0, len(ang), 45):
+        parts.append(orc.forward(geo, ang[v0:v0 + 45], x_gt.astype(np.float64), "interp"))
+        print(f"oracle A x: views {v0}-{v0 + len(parts[-1]) - 1} of {len(ang)}", flush=True)
+    b_clean = np.concatenate(parts)
+    del parts
+    assert np.allclose(b_clean[rays[0], rays[1], rays[2]], g["b_clean_rays"], rtol=1e-12, atol=0.0)
+    b = synth.poisson_log_data(b_clean, meta["noise_seed"], I0=meta["I0"])
     del b_clean
-    bn = b[rays[0], rays[1], rays[2]]
-    moved = np.abs(bn - g["b_rays"]) > 1e-4 * np.abs(g["b_rays"]).max()
-    assert moved.mean() < 0.01, moved.mean()
+    assert np.allclose(b[rays[0], rays[1], rays[2]], g["b_rays"], rtol=1e-12, atol=0.0)
     return dict(geo=geo, ang=ang, plan=plan, b=torch.from_numpy(b.astype(np.float32)).cuda(), gold=have)
 
 

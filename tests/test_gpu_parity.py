@@ -154,6 +154,24 @@ def test_fdk_filter_every_fft_length(P, orc, nu):
     assert _rel(got, want) < 1e-5, (nu, _rel(got, want))
 
 
+@pytest.mark.parametrize("nv,nu,nviews", [(512, 512, 360), (65, 200, 301)])
+def test_fdk_filter_many_rows_sampled_views(P, orc, nv, nu, nviews):
+    """Enough rows that the persistent workgroups loop over several groups
+    of row pairs, for the lengths that pack two (L = 1024) and four
+    (L = 512) row pairs per workgroup; the second case has an odd row count
+    and a last group with one pair missing.  Sampled views against the
+    oracle, the last view included."""
+    geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(nv, nu),
+                   dDetector=(0.8, 0.8), offDetector=(0.4, -1.3))
+    ang = synth.circular_angles(nviews)
+    y = synth.uniform_projections(geo, nviews, 90 + nv)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.fdk_filter(_dev(y)))
+    for k in (0, 1, nviews // 2, nviews - 2, nviews - 1):
+        want = orc.fdk_filter(geo, y[k:k + 1].astype(np.float64), ntotal=nviews)
+        assert _rel(got[k], want) < 1e-5, (nv, nu, k, _rel(got[k], want))
+
+
 def test_bfdk_matches_oracle(P, orc):
     geo, ang = RAGGED, _angles(24, 12)
     y = synth.uniform_projections(geo, len(ang), 13)
