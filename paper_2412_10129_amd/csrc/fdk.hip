@@ -35,17 +35,30 @@ constexpr int FDK_TX = CTMI_FDK_TX, FDK_TY = 256 / FDK_TX, FDK_ZC = CTMI_FDK_ZC;
 #ifndef CTMI_FDK_CAP
 #define CTMI_FDK_CAP 2560
 #endif
+#ifndef CTMI_FDK_P
+#define CTMI_FDK_P 64
+#endif
 constexpr int FDK_VB = CTMI_FDK_VB, FDK_CAP = CTMI_FDK_CAP;
+// Row pitch of a staged footprint up to FDK_P pixels wide: a compile-time
+// pitch puts a voxel's four taps at one address plus immediate offsets
+// (two paired LDS reads).
+constexpr int FDK_P = CTMI_FDK_P;
+static_assert(FDK_P + 1 <= 255, "paired-read offsets are 8-bit dword counts");
 #ifndef CTMI_FDK_XCD
 #define CTMI_FDK_XCD 0
 #endif
 
 struct FdkBox {
     int u0, v0, w, h;   // staged pixels [u0, u0 + w) x [v0, v0 + h); w = 0: not staged
+    int pitch;          // LDS row pitch (floats): FDK_P when w <= FDK_P and it fits, else w
     float rw;           // 1 / w
+    int inner;          // pitch FDK_P and no margin clipped by the detector (below)
 };
 
-__global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __restrict__ proj,
+#ifndef CTMI_FDK_WAVES
+#define CTMI_FDK_WAVES 6
+#endif
+__global__ void __launch_bounds__(FDK_TX* FDK_TY) __attribute__((amdgpu_waves_per_eu(CTMI_FDK_WAVES, 8))) k_backward_fdk(const float* __restrict__ proj,
                                                                  float* __restrict__ vol,
                                                                  const ViewGeo* __restrict__ tab, int view0,
                                                                  int nviews, VolDims v, DetDims det, int nbx,
@@ -90,7 +103,9 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
             FdkBox f;
             f.w = 0;
             f.u0 = f.v0 = f.h = 0;
+            f.pitch = 0;
             f.rw = 1.0f;
+            f.inner = 0;
             // clamp in float first: corners may project far off the detector
             umin = fminf(fmaxf(umin, -4.0f), (float)det.nu + 4.0f);
             umax = fminf(fmaxf(umax, -4.0f), (float)det.nu + 4.0f);
@@ -98,14 +113,30 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
             vmax = fminf(fmaxf(vmax, -4.0f), (float)det.nv + 4.0f);
             const int u0 = max((int)__builtin_floorf(umin) - 1, 0), u1 = min((int)__builtin_floorf(umax) + 2, det.nu - 1);
             const int v0 = max((int)__builtin_floorf(vmin) - 1, 0), v1 = min((int)__builtin_floorf(vmax) + 2, det.nv - 1);
+            // a voxel of the block projects inside the corners' bounding
+            // box (all in front of the source; on a circular orbit u does
+            // not depend on z), so its taps floor(u), floor(u) + 1 lie in
+            // [floor(umin) - 1, floor(umax) + 2], and the same for v, with a
+            // pixel to spare for rounding: when no end was clipped, every tap
+            // is on the detector and in the box.  (A block cut by the
+            // volume's last z plane still runs its threads past it, outside
+            // [lo, hi]: it keeps the clamped taps.)
+            const bool inner = (int)__builtin_floorf(vmin) - 1 >= 0 && (int)__builtin_floorf(vmax) + 2 <= det.nv - 1 &&
+                               (int)__builtin_floorf(umin) - 1 >= 0 && (int)__builtin_floorf(umax) + 2 <= det.nu - 1 &&
+                               iz0 + FDK_ZC <= v.nz;
             // (each side is checked first, so the product cannot overflow)
-            if (wmin > 0.0f && u0 <= u1 && v0 <= v1 && u1 - u0 < FDK_CAP && v1 - v0 < FDK_CAP &&
-                (u1 - u0 + 1) * (v1 - v0 + 1) <= FDK_CAP) {
-                f.u0 = u0;
-                f.v0 = v0;
-                f.w = u1 - u0 + 1;
-                f.h = v1 - v0 + 1;
-                f.rw = 1.0f / (float)f.w;
+            if (wmin > 0.0f && u0 <= u1 && v0 <= v1 && u1 - u0 < FDK_CAP && v1 - v0 < FDK_CAP) {
+                const int w = u1 - u0 + 1, h = v1 - v0 + 1;
+                const int pitch = w <= FDK_P && h * FDK_P <= FDK_CAP ? FDK_P : w;
+                if (h * pitch <= FDK_CAP) {
+                    f.u0 = u0;
+                    f.v0 = v0;
+                    f.w = w;
+                    f.h = h;
+                    f.pitch = pitch;
+                    f.rw = 1.0f / (float)w;
+                    f.inner = inner && pitch == FDK_P ? 1 : 0;
+                }
             }
             fb[threadIdx.x] = f;
         }
@@ -118,7 +149,7 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 // row i / w from FP32 ((i + 1/2) / w is at least 1/(2w) from an integer)
                 const int r = (int)(((float)i + 0.5f) * f.rw);
-                box[q][i] = pk[(int64_t)(f.v0 + r) * det.nu + f.u0 + (i - r * f.w)];
+                box[q][r * f.pitch + (i - r * f.w)] = pk[(int64_t)(f.v0 + r) * det.nu + f.u0 + (i - r * f.w)];
             }
         }
         __syncthreads();
@@ -142,9 +173,29 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
             const FdkBox f = fb[q];
             if (f.w > 0) {
                 // staged: LDS offsets clamped into the box (a no-op when the
-                // footprint holds the taps, which its margins ensure)
+                // footprint holds the taps, which its margins ensure); the
+                // columns once per view, the rows per voxel unless the box
+                // holds every row the block can tap
                 const int c0 = min(max(u0 - f.u0, 0), f.w - 1), c1 = min(max(u1 - f.u0, 0), f.w - 1);
                 const float* bq = box[q];
+                if (f.inner) {
+                    // every tap lies in the box and on the detector (above):
+                    // no clamps and no zero weights (wu0, wu1 are 1 - au, au);
+                    // the row offset is an exact FP32 integer (below 2^24)
+                    const float v0f = (float)f.v0;
+                    const float* b = bq + (iu - f.u0);
+#pragma unroll
+                    for (int z = 0; z < FDK_ZC; ++z) {
+                        const float fv = __builtin_fmaf((float)z, dfv, fv0);
+                        const float flv = __builtin_floorf(fv);
+                        const float av = fv - flv;
+                        const float* t = b + (int)((flv - v0f) * (float)FDK_P);
+                        const float s0 = __builtin_fmaf(wu0, t[0], wu1 * t[1]);
+                        const float s1 = __builtin_fmaf(wu0, t[FDK_P], wu1 * t[FDK_P + 1]);
+                        acc[z] = __builtin_fmaf(wt, __builtin_fmaf(1.0f - av, s0, av * s1), acc[z]);
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int z = 0; z < FDK_ZC; ++z) {
                     const float fv = __builtin_fmaf((float)z, dfv, fv0);
@@ -155,8 +206,8 @@ __global__ void __launch_bounds__(FDK_TX* FDK_TY) k_backward_fdk(const float* __
                     const float wv1 = (unsigned)(iv + 1) < (unsigned)det.nv ? av : 0.0f;
                     const int r0 = min(max(min(max(iv, 0), det.nv - 1) - f.v0, 0), f.h - 1);
                     const int r1 = min(max(min(max(iv + 1, 0), det.nv - 1) - f.v0, 0), f.h - 1);
-                    const float* p0 = bq + r0 * f.w;
-                    const float* p1 = bq + r1 * f.w;
+                    const float* p0 = bq + r0 * f.pitch;
+                    const float* p1 = bq + r1 * f.pitch;
                     const float s0 = __builtin_fmaf(wu0, p0[c0], wu1 * p0[c1]);
                     const float s1 = __builtin_fmaf(wu0, p1[c0], wu1 * p1[c1]);
                     acc[z] = __builtin_fmaf(wt, __builtin_fmaf(wv0, s0, wv1 * s1), acc[z]);
@@ -265,21 +316,25 @@ __device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y
 //
 // DIF pass over stages S, S/2, S/4 (E = S/4): butterfly t < L/8 takes
 // elements i0 + k E, k < 8, i0 = (t / E) 2S + t mod E.
-template <class LD, class ST>
-__device__ __forceinline__ void dif8(const float2* tw, int L, int S, LD ld, ST st)
+//
+// With Z (the first pass, S = L/2) the upper half of the row is the zero
+// padding (L >= 2 nu - 1), so inputs k >= 4 are not read and the first
+// stage's sums and differences are the inputs themselves.
+template <bool Z = false, class LD, class ST>
+__device__ __forceinline__ void dif8(const float2* tw, int L, int S, int t0, int dt, LD ld, ST st)
 {
     const int E = S >> 2, ts1 = L / (2 * S);
-    for (int t = threadIdx.x; t < (L >> 3); t += blockDim.x) {
+    for (int t = t0; t < (L >> 3); t += dt) {
         const int j = t & (E - 1);
         const int i0 = ((t - j) << 3) + j;
         float2 x[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = ld(i0 + k * E);
+        for (int k = 0; k < 8; ++k) x[k] = (Z && k >= 4) ? make_float2(0.0f, 0.0f) : ld(i0 + k * E);
         float2 y[8];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            y[k] = cadd(x[k], x[k + 4]);
-            y[k + 4] = cmul(csub(x[k], x[k + 4]), tw[(j + k * E) * ts1]);
+            y[k] = Z ? x[k] : cadd(x[k], x[k + 4]);
+            y[k + 4] = cmul(Z ? x[k] : csub(x[k], x[k + 4]), tw[(j + k * E) * ts1]);
         }
         const float2 c0 = tw[j * 2 * ts1], c1 = tw[(j + E) * 2 * ts1], c3 = tw[j * 4 * ts1];
 #pragma unroll
@@ -297,10 +352,10 @@ __device__ __forceinline__ void dif8(const float2* tw, int L, int S, LD ld, ST s
 // DIF pass over stages S, S/2 (Q = S/2): elements i0 + {0, Q, 2Q, 3Q},
 // i0 = (t / Q) 2S + t mod Q.
 template <class LD, class ST>
-__device__ __forceinline__ void dif4(const float2* tw, int L, int S, LD ld, ST st)
+__device__ __forceinline__ void dif4(const float2* tw, int L, int S, int t0, int dt, LD ld, ST st)
 {
     const int Q = S >> 1, ts = L / (2 * S);
-    for (int t = threadIdx.x; t < (L >> 2); t += blockDim.x) {
+    for (int t = t0; t < (L >> 2); t += dt) {
         const int j = t & (Q - 1);
         const int i0 = ((t - j) << 2) + j;
         const float2 x0 = ld(i0), x1 = ld(i0 + Q), x2 = ld(i0 + S), x3 = ld(i0 + S + Q);
@@ -316,9 +371,9 @@ __device__ __forceinline__ void dif4(const float2* tw, int L, int S, LD ld, ST s
 
 // DIF stage of span 1 (twiddle tw[0]).
 template <class LD, class ST>
-__device__ __forceinline__ void dif2(const float2* tw, int L, LD ld, ST st)
+__device__ __forceinline__ void dif2(const float2* tw, int L, int t0, int dt, LD ld, ST st)
 {
-    for (int t = threadIdx.x; t < (L >> 1); t += blockDim.x) {
+    for (int t = t0; t < (L >> 1); t += dt) {
         const float2 u = ld(2 * t), w = ld(2 * t + 1);
         st(2 * t, cadd(u, w));
         st(2 * t + 1, cmul(csub(u, w), tw[0]));
@@ -326,12 +381,14 @@ __device__ __forceinline__ void dif2(const float2* tw, int L, LD ld, ST st)
 }
 
 // DIT pass over stages S, 2S, 4S: elements i0 + k S, k < 8,
-// i0 = (t / S) 8S + t mod S.
-template <class LD, class ST>
-__device__ __forceinline__ void dit8(const float2* tw, int L, int S, LD ld, ST st)
+// i0 = (t / S) 8S + t mod S.  With H (the last pass, S = L/8) only the
+// lower half of the row is stored: the upper half is the padding's share of
+// the circular convolution, which the filtered row does not keep.
+template <bool H = false, class LD, class ST>
+__device__ __forceinline__ void dit8(const float2* tw, int L, int S, int t0, int dt, LD ld, ST st)
 {
     const int ts1 = L / (2 * S);
-    for (int t = threadIdx.x; t < (L >> 3); t += blockDim.x) {
+    for (int t = t0; t < (L >> 3); t += dt) {
         const int j = t & (S - 1);
         const int i0 = ((t - j) << 3) + j;
         float2 x[8];
@@ -359,17 +416,17 @@ __device__ __forceinline__ void dit8(const float2* tw, int L, int S, LD ld, ST s
         for (int k = 0; k < 4; ++k) {
             const float2 w = cmul(z[k + 4], conj2(tw[(j + k * S) * (ts1 >> 2)]));
             st(i0 + k * S, cadd(z[k], w));
-            st(i0 + (k + 4) * S, csub(z[k], w));
+            if (!H) st(i0 + (k + 4) * S, csub(z[k], w));
         }
     }
 }
 
 // DIT pass over stages S, 2S: elements i0 + {0, S, 2S, 3S}, i0 = (t / S) 4S + t mod S.
 template <class LD, class ST>
-__device__ __forceinline__ void dit4(const float2* tw, int L, int S, LD ld, ST st)
+__device__ __forceinline__ void dit4(const float2* tw, int L, int S, int t0, int dt, LD ld, ST st)
 {
     const int ts1 = L / (2 * S), ts2 = ts1 >> 1;
-    for (int t = threadIdx.x; t < (L >> 2); t += blockDim.x) {
+    for (int t = t0; t < (L >> 2); t += dt) {
         const int j = t & (S - 1);
         const int i0 = ((t - j) << 2) + j;
         const float2 c1 = conj2(tw[j * ts1]), ca = conj2(tw[j * ts2]), cb = conj2(tw[(j + S) * ts2]);
@@ -386,9 +443,9 @@ __device__ __forceinline__ void dit4(const float2* tw, int L, int S, LD ld, ST s
 
 // DIT stage of span 1 (twiddle conj(tw[0])).
 template <class LD, class ST>
-__device__ __forceinline__ void dit2(const float2* tw, int L, LD ld, ST st)
+__device__ __forceinline__ void dit2(const float2* tw, int L, int t0, int dt, LD ld, ST st)
 {
-    for (int t = threadIdx.x; t < (L >> 1); t += blockDim.x) {
+    for (int t = t0; t < (L >> 1); t += dt) {
         const float2 w = cmul(ld(2 * t + 1), conj2(tw[0]));
         const float2 u = ld(2 * t);
         st(2 * t, cadd(u, w));
@@ -397,31 +454,51 @@ __device__ __forceinline__ void dit2(const float2* tw, int L, LD ld, ST st)
 }
 
 // Workgroups are persistent over row pairs: each copies the twiddle table
-// to LDS once (when it fits, TWL) and then filters row pairs
-// blockIdx.x, blockIdx.x + gridDim.x, ...
-template <bool TWL, bool P = TWL>
+// to LDS once (when it fits, TWL) and then filters row pairs.  LOGL > 0
+// fixes the row length L = 2^LOGL at compile time (spans, twiddle strides
+// and the pass schedule become constants); LOGL = 0 takes it from the
+// arguments.  A pair takes TPP threads (one radix-8 butterfly each, at most
+// 256), so a workgroup holds 256 / TPP pairs, each in its own LDS row; pairs
+// g PPB + sub, g = blockIdx.x, blockIdx.x + gridDim.x, ...
+template <int LOGL>
+struct FilterShape {
+    static constexpr int TPP = LOGL == 0 ? 256 : ((1 << LOGL) / 8 < 256 ? (1 << LOGL) / 8 : 256);
+    static constexpr int PPB = 256 / TPP;
+};
+
+template <int LOGL, bool TWL, bool P = TWL>
 __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out, const float* __restrict__ H,
                                                     const float2* __restrict__ twg, int64_t nrows, FilterArgs fa)
 {
+    static_assert(LOGL == 0 || LOGL >= 6, "fixed lengths give every thread a butterfly");
+    constexpr int TPP = FilterShape<LOGL>::TPP, PPB = FilterShape<LOGL>::PPB;
     extern __shared__ float2 buf[];
-    const int L = fa.L, L2 = L >> 1, logL = fa.logL;
-    float2* const tws = buf + L + (P ? L >> 4 : 0);
+    const int L = LOGL ? 1 << LOGL : fa.L, L2 = L >> 1, logL = LOGL ? LOGL : fa.logL;
+    const int rowsz = L + (P ? L >> 4 : 0);
+    float2* const tws = buf + PPB * rowsz;
     const float2* const tw = TWL ? tws : twg;
     if (TWL)
         for (int n = threadIdx.x; n < L2; n += blockDim.x) tws[n] = twg[n];
-    auto lds_ld = [&](int i) { return buf[pad<P>(i)]; };
-    auto lds_st = [&](int i, float2 v) { buf[pad<P>(i)] = v; };
+    const int sub = PPB > 1 ? (int)threadIdx.x / TPP : 0;
+    const int t0 = PPB > 1 ? (int)threadIdx.x % TPP : (int)threadIdx.x;
+    const int dt = PPB > 1 ? TPP : (int)blockDim.x;
+    float2* const row = buf + sub * rowsz;
+    auto lds_ld = [&](int i) { return row[pad<P>(i)]; };
+    auto lds_st = [&](int i, float2 v) { row[pad<P>(i)] = v; };
     // the response (bit-reversed order, 1/L and tau folded in) times the
     // angular scale, applied as the last forward pass stores
     auto resp_st = [&](int i, float2 v) {
         const float h = H[i] * fa.scale;
-        buf[pad<P>(i)] = make_float2(v.x * h, v.y * h);
+        row[pad<P>(i)] = make_float2(v.x * h, v.y * h);
     };
     const int64_t npairs = (nrows + 1) / 2;
-    for (int64_t pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
+    for (int64_t g = blockIdx.x; g * PPB < npairs; g += gridDim.x) {
+        const int64_t pr = g * PPB + sub;
+        const bool live = pr < npairs;   // the last group may be partial
         const int64_t r0 = 2 * pr, r1 = r0 + 1;
-        const bool has1 = r1 < nrows;
-        const int iv0 = (int)(r0 % fa.nv), iv1 = (int)(r1 % fa.nv);
+        const bool has1 = live && r1 < nrows;
+        const int iv0 = (int)(r0 % fa.nv);
+        const int iv1 = iv0 + 1 == fa.nv ? 0 : iv0 + 1;
         const float* a = in + r0 * fa.nu;
         const float* bb = in + r1 * fa.nu;
         float* oa = out + r0 * fa.nu;
@@ -430,36 +507,78 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
         const float cv0 = row_const(fa, iv0), cv1 = row_const(fa, iv1);
         auto src = [&](int n) {
             float x = 0.0f, y = 0.0f;
-            if (n < fa.nu) {
+            if (live && n < fa.nu) {
                 x = a[n] * row_weight(fa, n, cv0);
                 if (has1) y = bb[n] * row_weight(fa, n, cv1);
             }
             return make_float2(x, y);
         };
         auto dst = [&](int n, float2 v) {
-            if (n < fa.nu) {
+            if (live && n < fa.nu) {
                 oa[n] = v.x;
                 if (has1) ob[n] = v.y;
             }
         };
-        __syncthreads();   // the previous pair is done with buf (and the twiddles are in)
-        if (logL >= 3) {
+        __syncthreads();   // the previous pairs are done with buf (and the twiddles are in)
+        if (LOGL > 0) {
+            // the last forward pass, the response and the first inverse pass
+            // act on the same G = 2, 4 or 8 consecutive elements per
+            // butterfly, so they run as one pass in registers (same
+            // arithmetic, one LDS round trip and one barrier fewer)
+            constexpr int R = LOGL % 3, G = R == 0 ? 8 : (R == 1 ? 2 : 4);
+            dif8<true>(tw, L, L2, t0, dt, src, lds_st);
+            __syncthreads();
+            for (int span = L2 >> 3; span > G / 2; span >>= 3) {
+                dif8(tw, L, span, t0, dt, lds_ld, lds_st);
+                __syncthreads();
+            }
+            for (int t = t0; t < L / G; t += dt) {
+                float2 r[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) r[k] = lds_ld(G * t + k);
+                auto rl = [&](int i) { return r[i & (G - 1)]; };
+                auto rs = [&](int i, float2 v) { r[i & (G - 1)] = v; };
+                auto rr = [&](int i, float2 v) {
+                    const float h = H[i] * fa.scale;
+                    r[i & (G - 1)] = make_float2(v.x * h, v.y * h);
+                };
+                if (G == 2) {
+                    dif2(tw, L, t, L, rl, rr);
+                    dit2(tw, L, t, L, rl, rs);
+                } else if (G == 4) {
+                    dif4(tw, L, 2, t, L, rl, rr);
+                    dit4(tw, L, 1, t, L, rl, rs);
+                } else {
+                    dif8(tw, L, 4, t, L, rl, rr);
+                    dit8(tw, L, 1, t, L, rl, rs);
+                }
+#pragma unroll
+                for (int k = 0; k < G; ++k) lds_st(G * t + k, r[k]);
+            }
+            __syncthreads();
+            int span = G;
+            for (; span < (L >> 3); span <<= 3) {
+                dit8(tw, L, span, t0, dt, lds_ld, lds_st);
+                __syncthreads();
+            }
+            dit8<true>(tw, L, span, t0, dt, lds_ld, dst);
+        } else if (logL >= 3) {
             // forward DIF from span L/2: radix-8 passes, then the one or two
             // stages left; the first reads the rows, the last applies the response
             int span = L2, rem = logL;
-            if (rem == 3) dif8(tw, L, span, src, resp_st);
-            else dif8(tw, L, span, src, lds_st);
+            if (rem == 3) dif8<true>(tw, L, span, t0, dt, src, resp_st);
+            else dif8<true>(tw, L, span, t0, dt, src, lds_st);
             __syncthreads();
             for (rem -= 3, span >>= 3; rem >= 3; rem -= 3, span >>= 3) {
-                if (rem == 3) dif8(tw, L, span, lds_ld, resp_st);
-                else dif8(tw, L, span, lds_ld, lds_st);
+                if (rem == 3) dif8(tw, L, span, t0, dt, lds_ld, resp_st);
+                else dif8(tw, L, span, t0, dt, lds_ld, lds_st);
                 __syncthreads();
             }
             if (rem == 2) {
-                dif4(tw, L, span, lds_ld, resp_st);
+                dif4(tw, L, span, t0, dt, lds_ld, resp_st);
                 __syncthreads();
             } else if (rem == 1) {
-                dif2(tw, L, lds_ld, resp_st);
+                dif2(tw, L, t0, dt, lds_ld, resp_st);
                 __syncthreads();
             }
             // inverse DIT from span 1: the one or two stages left over first,
@@ -467,30 +586,30 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
             span = 1;
             rem = logL % 3;
             if (rem == 1) {
-                dit2(tw, L, lds_ld, lds_st);
+                dit2(tw, L, t0, dt, lds_ld, lds_st);
                 __syncthreads();
                 span = 2;
             } else if (rem == 2) {
-                dit4(tw, L, 1, lds_ld, lds_st);
+                dit4(tw, L, 1, t0, dt, lds_ld, lds_st);
                 __syncthreads();
                 span = 4;
             }
             for (; span < (L >> 3); span <<= 3) {
-                dit8(tw, L, span, lds_ld, lds_st);
+                dit8(tw, L, span, t0, dt, lds_ld, lds_st);
                 __syncthreads();
             }
-            dit8(tw, L, span, lds_ld, dst);
+            dit8<true>(tw, L, span, t0, dt, lds_ld, dst);
         } else {
             // L = 2 or 4: one load pass, the stages, the response, the store
-            for (int n = threadIdx.x; n < L; n += blockDim.x) lds_st(n, src(n));
+            for (int n = t0; n < L; n += dt) lds_st(n, src(n));
             __syncthreads();
-            if (logL == 2) dif4(tw, L, L2, lds_ld, resp_st);
-            else dif2(tw, L, lds_ld, resp_st);
+            if (logL == 2) dif4(tw, L, L2, t0, dt, lds_ld, resp_st);
+            else dif2(tw, L, t0, dt, lds_ld, resp_st);
             __syncthreads();
-            if (logL == 2) dit4(tw, L, 1, lds_ld, lds_st);
-            else dit2(tw, L, lds_ld, lds_st);
+            if (logL == 2) dit4(tw, L, 1, t0, dt, lds_ld, lds_st);
+            else dit2(tw, L, t0, dt, lds_ld, lds_st);
             __syncthreads();
-            for (int n = threadIdx.x; n < L; n += blockDim.x) dst(n, lds_ld(n));
+            for (int n = t0; n < L; n += dt) dst(n, lds_ld(n));
         }
     }
 }
@@ -530,18 +649,32 @@ hipError_t launch_fdk_filter(const Plan& p, int wang, const float* proj, float* 
     fa.wang_D = (float)(0.5 * (double)p.det.nu * g.dDetector[1] - (g.offDetector[1] < 0 ? -g.offDetector[1] : g.offDetector[1]));
     fa.wang_sign = g.offDetector[1] < 0 ? -1.0f : 1.0f;
     const int64_t nrows = nviews * p.det.nv;
+    const int64_t npairs = (nrows + 1) / 2;
     // persistent workgroups: enough for 8 per CU, each looping over row pairs
-    const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 1) / 2, 2048);
-    // up to L = 4096 the padded row and the twiddle table in LDS (51 KB)
+    auto groups = [&](int ppb) { return (unsigned)std::min<int64_t>((npairs + ppb - 1) / ppb, 2048); };
+    // up to L = 4096 the padded rows and the twiddle table in LDS (51 KB)
     const size_t row = (size_t)p.fft_len + (size_t)(p.fft_len >> 4);   // padded row
-    if (p.fft_len <= 4096) {
-        const size_t lds = sizeof(float2) * (row + (size_t)p.fft_len / 2);
-        hipLaunchKernelGGL(k_fdk_filter<true>, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle,
-                           nrows, fa);
-    } else {   // L = 8192: the unpadded row alone fills 64 KB
-        const size_t lds = sizeof(float2) * (size_t)p.fft_len;
-        hipLaunchKernelGGL(k_fdk_filter<false>, dim3(blocks), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle,
-                           nrows, fa);
+    const size_t tws = (size_t)p.fft_len / 2;
+    auto fixed = [&](auto kern, int ppb) {
+        const size_t lds = sizeof(float2) * ((size_t)ppb * row + tws);
+        hipLaunchKernelGGL(kern, dim3(groups(ppb)), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle, nrows,
+                           fa);
+    };
+    switch (p.fft_log2) {
+    case 9: fixed(k_fdk_filter<9, true>, FilterShape<9>::PPB); break;
+    case 10: fixed(k_fdk_filter<10, true>, FilterShape<10>::PPB); break;
+    case 11: fixed(k_fdk_filter<11, true>, FilterShape<11>::PPB); break;
+    case 12: fixed(k_fdk_filter<12, true>, FilterShape<12>::PPB); break;
+    default:
+        if (p.fft_len <= 4096) {
+            const size_t lds = sizeof(float2) * (row + tws);
+            hipLaunchKernelGGL((k_fdk_filter<0, true>), dim3(groups(1)), dim3(256), lds, s, proj, out, p.d_filter,
+                               p.d_twiddle, nrows, fa);
+        } else {   // L = 8192: the unpadded row alone fills 64 KB
+            const size_t lds = sizeof(float2) * (size_t)p.fft_len;
+            hipLaunchKernelGGL((k_fdk_filter<0, false>), dim3(groups(1)), dim3(256), lds, s, proj, out, p.d_filter,
+                               p.d_twiddle, nrows, fa);
+        }
     }
     return hipGetLastError();
 }
