@@ -297,6 +297,19 @@ __device__ __forceinline__ float row_weight(const FilterArgs& fa, int iu, float 
 template <bool P>
 __device__ __forceinline__ int pad(int i) { return P ? i + (i >> 4) : i; }
 
+// LDS slot of row element i for the compile-time lengths: bits 5-7 of i
+// are XORed into bits 2-4 and 0-2 (a permutation within each 32-element
+// block), which spreads the strided and the contiguous small-span accesses
+// over the banks without padding.
+#ifndef CTMI_FILTER_SWZ
+#define CTMI_FILTER_SWZ 1
+#endif
+__device__ __forceinline__ int swz(int i)
+{
+    const int g = (i >> 5) & 7;
+    return i ^ (g << 2) ^ g;
+}
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 conj2(float2 a) { return make_float2(a.x, -a.y); }
@@ -474,7 +487,8 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
     constexpr int TPP = FilterShape<LOGL>::TPP, PPB = FilterShape<LOGL>::PPB;
     extern __shared__ float2 buf[];
     const int L = LOGL ? 1 << LOGL : fa.L, L2 = L >> 1, logL = LOGL ? LOGL : fa.logL;
-    const int rowsz = L + (P ? L >> 4 : 0);
+    constexpr bool SWZ = LOGL > 0 && CTMI_FILTER_SWZ != 0;
+    const int rowsz = L + (P && !SWZ ? L >> 4 : 0);
     float2* const tws = buf + PPB * rowsz;
     const float2* const tw = TWL ? tws : twg;
     if (TWL)
@@ -483,13 +497,14 @@ __global__ void __launch_bounds__(256) k_fdk_filter(const float* in, float* out,
     const int t0 = PPB > 1 ? (int)threadIdx.x % TPP : (int)threadIdx.x;
     const int dt = PPB > 1 ? TPP : (int)blockDim.x;
     float2* const row = buf + sub * rowsz;
-    auto lds_ld = [&](int i) { return row[pad<P>(i)]; };
-    auto lds_st = [&](int i, float2 v) { row[pad<P>(i)] = v; };
+    auto slot = [&](int i) { return SWZ ? swz(i) : pad<P>(i); };
+    auto lds_ld = [&](int i) { return row[slot(i)]; };
+    auto lds_st = [&](int i, float2 v) { row[slot(i)] = v; };
     // the response (bit-reversed order, 1/L and tau folded in) times the
     // angular scale, applied as the last forward pass stores
     auto resp_st = [&](int i, float2 v) {
         const float h = H[i] * fa.scale;
-        row[pad<P>(i)] = make_float2(v.x * h, v.y * h);
+        row[slot(i)] = make_float2(v.x * h, v.y * h);
     };
     const int64_t npairs = (nrows + 1) / 2;
     for (int64_t g = blockIdx.x; g * PPB < npairs; g += gridDim.x) {
@@ -656,7 +671,8 @@ hipError_t launch_fdk_filter(const Plan& p, int wang, const float* proj, float* 
     const size_t row = (size_t)p.fft_len + (size_t)(p.fft_len >> 4);   // padded row
     const size_t tws = (size_t)p.fft_len / 2;
     auto fixed = [&](auto kern, int ppb) {
-        const size_t lds = sizeof(float2) * ((size_t)ppb * row + tws);
+        const size_t frow = CTMI_FILTER_SWZ ? (size_t)p.fft_len : row;   // swizzled rows need no padding
+        const size_t lds = sizeof(float2) * ((size_t)ppb * frow + tws);
         hipLaunchKernelGGL(kern, dim3(groups(ppb)), dim3(256), lds, s, proj, out, p.d_filter, p.d_twiddle, nrows,
                            fa);
     };
