@@ -151,7 +151,7 @@ def evaluate(plan: Plan, net: UNet, vols, niter: int = 60, every: int = 5, ratio
     With `on_run`, every iterate of both runs is kept on the device and
     on_run(n, x_gt_host, res, iterates) is called per volume with
     iterates = {"cgls": [...], "pnp": [...]} (device tensors, freed after
-    the call), e.g. to judge them independently."""
+    the call), e.g. to score them independently."""
     runs = []
     geo = plan.geo
     for n, v in enumerate(vols):
