@@ -29,7 +29,8 @@ def _addr(t: torch.Tensor, i: int, j: int) -> int:
 
 
 def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Optional[torch.Tensor] = None,
-         x0: Optional[torch.Tensor] = None, sync: bool = True, snapshots=(), callback=None):
+         x0: Optional[torch.Tensor] = None, sync: bool = True, snapshots=(), callback=None,
+         state: Optional[dict] = None):
     """CGLS (Hestenes-Stiefel; the Krylov solvers of section 2.2.1).
 
     x0 = 0 (or the given start); r = b - A x0; s = A^T r; p = s; gamma = |s|^2;
@@ -43,25 +44,43 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
     the iterate after k iterations for every k in `snapshots`.  `callback(k,
     x)`, if given, runs on the host after iteration k (k = 1..niter) has been
     queued, with the iterate's device tensor (it may synchronize).
+
+    hist["state"] is the resumable state after the last iteration: the
+    iterate x, the residual r, the direction p, gamma = |A^T r|^2 (FP64, on
+    the device) and the iteration count k.  Passing it back as `state`
+    (possibly after save_state / load_state) continues the same iteration
+    bit for bit: iteration numbers for `snapshots` and `callback` then count
+    from state["k"].
     """
     dev = plan.device
     vol_shape, proj_shape = plan.vol_shape, plan.proj_shape()
     ws = ops._ws(dev)
     sc = torch.zeros((niter + 1, 3), dtype=torch.float64, device=dev)   # gamma_k, delta_k, |r_k|^2
     err = torch.zeros((niter, 2), dtype=torch.float64, device=dev)
-    if x0 is None:
-        x = torch.zeros(vol_shape, dtype=torch.float32, device=dev)
-        r = b.clone()
+    k0 = 0
+    if state is not None:
+        if x0 is not None:
+            raise ValueError("cgls: give either x0 or state")
+        x, r, p = (state[n].to(dev, torch.float32).clone() for n in ("x", "r", "p"))
+        if x.shape != vol_shape or p.shape != vol_shape or r.shape != b.shape:
+            raise ValueError("cgls: state shapes do not match the plan and b")
+        sc[0, 0] = state["gamma"].to(dev, torch.float64).reshape(())
+        k0 = int(state["k"])
+        s = torch.empty_like(p)
     else:
-        x = x0.clone()
-        r = plan.forward(x, kind=kind)
-        ops.axpby(1.0, b, -1.0, r)
-    s = plan.backproject(r, kind=kind)
-    p = s.clone()
+        if x0 is None:
+            x = torch.zeros(vol_shape, dtype=torch.float32, device=dev)
+            r = b.clone()
+        else:
+            x = x0.clone()
+            r = plan.forward(x, kind=kind)
+            ops.axpby(1.0, b, -1.0, r)
+        s = plan.backproject(r, kind=kind)
+        p = s.clone()
+        ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(s, "s"), ops._ptr(s, "s"), s.numel(), _addr(sc, 0, 0),
+                                         ws.data_ptr(), ws.numel() * 8, ops._stream()))
     q = torch.empty(proj_shape, dtype=torch.float32, device=dev)
     snaps = {int(k): None for k in snapshots}
-    ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(s, "s"), ops._ptr(s, "s"), s.numel(), _addr(sc, 0, 0),
-                                     ws.data_ptr(), ws.numel() * 8, ops._stream()))
     for k in range(niter):
         plan.forward(p, out=q, kind=kind)
         ops.L.check(ops.L.lib().ctmi_dot(ops._ptr(q, "q"), ops._ptr(q, "q"), q.numel(), _addr(sc, k, 1),
@@ -73,16 +92,18 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
         ops.cgls_p(p, s, _addr(sc, k, 0), _addr(sc, k + 1, 0))
         if x_gt is not None:
             plan.fov_sq_err(x, x_gt, err[k])
-        if k + 1 in snaps:
-            snaps[k + 1] = x.clone()
+        if k0 + k + 1 in snaps:
+            snaps[k0 + k + 1] = x.clone()
         if callback is not None:
-            callback(k + 1, x)
-    hist = {"scalars": sc, "err": err, "snapshots": snaps}
+            callback(k0 + k + 1, x)
+    st = {"x": x, "r": r, "p": p, "gamma": sc[niter, 0].clone(), "k": k0 + niter}
+    hist = {"scalars": sc, "err": err, "snapshots": snaps, "state": st}
     if sync:
         h = sc.cpu().numpy()
         hist = {"gamma": h[:, 0], "delta": h[:niter, 1], "resid": np.sqrt(h[:niter, 2]),
                 "alpha": h[:niter, 0] / np.where(h[:niter, 1] != 0, h[:niter, 1], np.inf),
-                "beta": h[1:, 0] / np.where(h[:niter, 0] != 0, h[:niter, 0], np.inf), "snapshots": snaps}
+                "beta": h[1:, 0] / np.where(h[:niter, 0] != 0, h[:niter, 0], np.inf), "snapshots": snaps,
+                "state": st}
         stop = np.nonzero((h[:niter, 1] == 0) | (h[:niter, 0] == 0))[0]
         hist["stopped"] = int(stop[0]) if len(stop) else None
         if x_gt is not None:
@@ -90,6 +111,19 @@ def cgls(plan: Plan, b: torch.Tensor, niter: int, kind: str = "interp", x_gt: Op
             hist["sq_err"] = e[:, 0]
             hist["count"] = e[:, 1]
     return x, hist
+
+
+def save_state(state: dict, f) -> None:
+    """Write a solver state (tensors and integers, e.g. cgls's hist["state"]
+    or an OS-SART checkpoint) with torch.save, tensors moved to the host."""
+    torch.save({k: (v.detach().cpu() if isinstance(v, torch.Tensor) else v) for k, v in state.items()}, f)
+
+
+def load_state(f, device=None) -> dict:
+    """Read a state written by save_state (tensors only, no code: the safe
+    loader), tensors on `device`."""
+    sd = torch.load(f, map_location="cpu", weights_only=True)
+    return {k: (v.to(device) if isinstance(v, torch.Tensor) and device is not None else v) for k, v in sd.items()}
 
 
 def psnr_from_sq_err(sq_err, count, data_range: float):
@@ -128,16 +162,29 @@ class OSSART:
         self._e = torch.empty(plan.proj_shape(mb), dtype=torch.float32, device=dev)
         self._bp = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
 
-    def sweep(self, x: torch.Tensor, b: torch.Tensor, lam: float = 1.0, nonneg: bool = True) -> torch.Tensor:
-        """One pass over all blocks, in place on x."""
+    def sweep(self, x: torch.Tensor, b: torch.Tensor, lam: float = 1.0, nonneg: bool = True, first: int = 0,
+              last: Optional[int] = None) -> torch.Tensor:
+        """One pass over the blocks first..last-1 (all by default), in place
+        on x.  A pass stopped after block j resumes from the iterate and
+        first = j + 1 (checkpoint()) bit for bit."""
         plan = self.plan
-        for s, (v0, nb) in enumerate(self.blocks):
+        last = len(self.blocks) if last is None else last
+        if not 0 <= first <= last <= len(self.blocks):
+            raise ValueError("OSSART.sweep: block range out of bounds")
+        for s in range(first, last):
+            v0, nb = self.blocks[s]
             e = self._e[:nb]
             plan.forward(x, out=e, kind=self.kind, view0=v0, nviews=nb)
             ops.sart_residual(b[v0:v0 + nb], e, self.W[v0:v0 + nb], e)
             plan.backproject(e, out=self._bp, kind=self.kind, view0=v0, nviews=nb)
             ops.sart_update(x, self.V[s], self._bp, lam, nonneg)
         return x
+
+    @staticmethod
+    def checkpoint(x: torch.Tensor, passes: int, next_block: int) -> dict:
+        """Resumable OS-SART state: the iterate, the completed passes and the
+        next block of the current pass."""
+        return {"x": x, "passes": int(passes), "next_block": int(next_block)}
 
     def run(self, b: torch.Tensor, niter: int, lam: float = 1.0, nonneg: bool = True,
             x0: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -115,10 +115,11 @@ def make_pairs(plan: Plan, dense: Plan, vols, kind: str = "interp", ks=KS, dense
 
 
 def train(net: UNet, inputs, targets, steps: int, crop: int = 64, batch: int = 4, seed: int = 0,
-          log_every: int = 100, log=print) -> List[float]:
+          log_every: int = 100, log=print, rng: Optional[np.random.Generator] = None) -> List[float]:
     """Adam on random crops; returns the per-step MSE (host floats, read
-    every `log_every` steps)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    every `log_every` steps).  Crops are drawn from `rng` (advanced in
+    place) if given, else from a PCG64 stream seeded with `seed`."""
+    rng = np.random.Generator(np.random.PCG64(seed)) if rng is None else rng
     D, H, W = inputs[0].shape
     xb = torch.empty((batch, crop, crop, crop), dtype=torch.float32, device=net.device)
     tb = torch.empty_like(xb)
@@ -187,6 +188,24 @@ def evaluate(plan: Plan, net: UNet, vols, niter: int = 60, every: int = 5, ratio
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_sparse256.pt")
+
+
+def training_checkpoint(net: UNet, rng: np.random.Generator) -> Dict:
+    """Everything a training run resumes from: the FP32 parameters, the Adam
+    moments and step, and the crop sampler's generator state (as JSON), all
+    on the host (torch.save it; the safe loader reads it back)."""
+    sd = {k: (v.detach().cpu() if isinstance(v, torch.Tensor) else v) for k, v in net.state_dict().items()}
+    sd["rng"] = json.dumps(rng.bit_generator.state)
+    return sd
+
+
+def restore_training(net: UNet, sd: Dict) -> np.random.Generator:
+    """Load a training_checkpoint into `net`; returns the crop sampler at the
+    state it was saved in, so that training continues bit for bit."""
+    net.load_state_dict({k: sd[k] for k in ("params", "m", "v", "t")})
+    rng = np.random.Generator(np.random.PCG64())
+    rng.bit_generator.state = json.loads(sd["rng"])
+    return rng
 
 
 def save_weights(params: torch.Tensor, path: str, meta: Dict) -> None:

@@ -237,6 +237,23 @@ def test_cgls_matches_oracle(P, orc):
     assert np.allclose(psnr, ho["psnr"], atol=0.01)
 
 
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_cgls_breakdown_flag(P, orc, kind):
+    """Data on rays that miss the volume (A^T b = 0): the device iteration
+    takes no step (its alpha and beta guard 0/0), the iterate stays exactly 0
+    and the history flags the breakdown at iteration 0, as the oracle's."""
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 40),
+                   dDetector=(1.6, 1.6))
+    ang = synth.circular_angles(4)
+    b = np.zeros((4,) + geo.nDetector, dtype=np.float32)
+    b[:, :, :4] = 1.0
+    b[:, :, -4:] = 2.0
+    _, ho = orc.cgls(geo, ang, b, 5, kind)
+    xg, hg = P.cgls(P.Plan(geo, ang), _dev(b), 5, kind=kind)
+    assert ho["stopped"] == 0 and hg["stopped"] == 0
+    assert not torch.any(xg) and np.all(np.isfinite(hg["resid"]))
+
+
 @pytest.mark.parametrize("blocksize,nonneg", [(8, True), (1, False), (24, True)])
 def test_os_sart_matches_oracle(P, orc, blocksize, nonneg):
     geo = Geometry(DSD=400.0, DSO=250.0, nVoxel=(20, 24, 28), dVoxel=(1.0, 1.0, 1.0), nDetector=(30, 40),

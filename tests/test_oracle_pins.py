@@ -425,6 +425,32 @@ def test_cgls_iterates_are_krylov_minimisers(orc, kind):
     assert all(res[i + 1] <= res[i] * (1 + 1e-12) for i in range(len(res) - 1))
 
 
+def _missing_rays_problem():
+    """A detector much wider than the volume's shadow, with data only on
+    columns whose rays miss the volume: A^T b = 0."""
+    geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 40),
+                   dDetector=(1.6, 1.6))
+    ang = synth.circular_angles(4)
+    b = np.zeros((4,) + geo.nDetector)
+    b[:, :, :4] = 1.0
+    b[:, :, -4:] = 2.0
+    return geo, ang, b
+
+
+@pytest.mark.parametrize("kind", ["siddon", "interp"])
+def test_cgls_breakdown_stops_at_once(orc, kind):
+    """CGLS breakdown (gamma = |A^T r|^2 = 0 before the first step): the run
+    stops at iteration 0 with the flag set and x = 0, for b = 0 and for data
+    the operator's range cannot see (rays that miss the volume; checked with
+    the dense matrix).  A step taken anyway would divide 0 by 0."""
+    geo, ang, b = _missing_rays_problem()
+    M = orc.dense_matrix(geo, ang, kind)
+    assert np.all(M[b.ravel() != 0] == 0) and np.any(M != 0)
+    for data in (np.zeros_like(b), b):
+        x, hist = orc.cgls(geo, ang, data, 5, kind)
+        assert hist["stopped"] == 0 and hist["resid"] == [] and not np.any(x)
+
+
 def test_cgls_norm_of_iterate_grows(orc):
     geo = Geometry(DSD=60.0, DSO=40.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(8, 8),
                    dDetector=(1.6, 1.6))
