@@ -141,9 +141,10 @@ def test_fdk_filter_wang_and_odd_rows(P, orc):
 @pytest.mark.parametrize("nu", [1, 2, 3, 5, 9, 17, 100, 200, 300, 700, 1500, 2100])
 def test_fdk_filter_every_fft_length(P, orc, nu):
     """Detector widths whose padded FFT lengths run from 2 to 8192: every
-    mix of radix-8, radix-4 and radix-2 passes, the padded LDS row with LDS
-    twiddles up to 4096 and the unpadded row with global twiddles at 8192;
-    three rows leave one unpaired."""
+    mix of radix-8, radix-4 and radix-2 passes, the compile-time instances
+    (L = 512 ... 4096: swizzled rows, 2-4 row pairs per workgroup below 2048)
+    and the general kernel (padded row with LDS twiddles below 512, unpadded
+    row with global twiddles at 8192); three rows leave one unpaired."""
     geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(8, 8, 8), dVoxel=(1.0, 1.0, 1.0), nDetector=(3, nu),
                    dDetector=(0.5, 0.5))
     ang = synth.circular_angles(2)
@@ -179,6 +180,38 @@ def test_bfdk_matches_oracle(P, orc):
     got = _host(plan.backproject(_dev(y), kind="fdk"))
     want = orc.bfdk(geo, ang, y)
     assert _rel(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("case", ["wide", "fine", "edges"])
+def test_bfdk_staging_paths_vs_oracle(P, orc, case):
+    """The backprojector's footprint paths against the oracle on sampled
+    voxels, half of them at the volume's corners and last z planes: 'wide'
+    (1 mm voxels on 0.8 x 0.6 mm pixels: footprints up to 68 pixels wide and
+    45 rows tall, staged at their own width), 'fine' (0.1 mm pixels:
+    footprints beyond the LDS capacity, read from global memory), 'edges' (a
+    detector that clips the footprints of the outer blocks, and a volume
+    height that cuts the last z block: the clamped taps beside the interior
+    fast path)."""
+    if case == "wide":
+        geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(64, 96, 96), dVoxel=(1.0, 1.0, 1.0), nDetector=(160, 160),
+                       dDetector=(0.6, 0.8))
+    elif case == "fine":
+        geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(32, 48, 48), dVoxel=(1.0, 1.0, 1.0), nDetector=(320, 480),
+                       dDetector=(0.1, 0.1), offDetector=(1.0, -2.0))
+    else:
+        geo = Geometry(DSD=1536.0, DSO=1000.0, nVoxel=(45, 128, 128), dVoxel=(0.5, 0.5, 0.5), nDetector=(80, 150),
+                       dDetector=(0.512, 0.512), offDetector=(3.0, 10.0))
+    ang = _angles(20, 31)
+    y = synth.uniform_projections(geo, len(ang), 32)
+    plan = P.Plan(geo, ang)
+    got = _host(plan.backproject(_dev(y), kind="fdk"))
+    rng = np.random.Generator(np.random.PCG64(33))
+    nz, ny, nx = geo.nVoxel
+    iz = np.concatenate([rng.integers(0, nz, 48), rng.choice([0, nz - 1, nz - 2], 48)])
+    iy = np.concatenate([rng.integers(0, ny, 48), rng.choice([0, ny - 1], 48)])
+    ix = np.concatenate([rng.integers(0, nx, 48), rng.choice([0, nx - 1], 48)])
+    want = orc.bfdk_voxels(geo, ang, y, iz, iy, ix)
+    assert _rel(got[iz, iy, ix], want) < 1e-5, (case, _rel(got[iz, iy, ix], want))
 
 
 def test_fdk_head64_end_to_end(P, orc):
