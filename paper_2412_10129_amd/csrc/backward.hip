@@ -15,16 +15,14 @@
 //
 // Accumulation is in fixed point in LDS: FP32 LDS atomics are serialised
 // on gfx950 (about 0.3 lane-ops per CU clock) while integer LDS atomics run
-// 30-45x faster.  Views are taken in groups of 8.  Siddon (one atomic per
-// segment): one power-of-two scale per (brick, group) from the footprints'
-// max |y| keeps every contribution within an int32 at 2^-30 of the largest
-// one, and 64-bit cells sum the whole group exactly.  Interpolated (eight
-// atomics per sample): the scale is chosen per round of 512 rays so that
-// everything the round can add to one cell fits an int32 (one ray adds at
-// most K ds |y| to a cell, K the most samples of a ray inside a 2x2x2-voxel
-// support, so the bound is K ds sum |y| over the round's rays); 32-bit
-// cells (about 1.4x faster atomics) hold the round's exact integer sum and
-// are flushed after every round.  Flushes convert the integer sums (exact
+// 30-45x faster.  Views are taken in groups of 8.  The scale is chosen per
+// round of rays (256 for Siddon, 512 interpolated) so that everything the
+// round can add to one cell fits an int32: a Siddon ray adds at most one
+// chord times |y| to a cell (it crosses a cell once); an interpolated ray at
+// most K ds |y|, K the most samples of a ray inside a 2x2x2-voxel support;
+// so the bound is that factor times the round's sum of |y|.  32-bit cells
+// (about 1.4x faster atomics than 64-bit ones) hold the round's exact
+// integer sum and are flushed after every round.  Flushes convert the integer sums (exact
 // power-of-two scaling) into per-thread FP32 registers in a fixed order;
 // integer addition is associative, so the result is bit-reproducible.
 //
@@ -334,16 +332,18 @@ __device__ __forceinline__ void store_owned(float* __restrict__ vol, const float
     }
 }
 
-// Accumulator cells.  Siddon: 64-bit cells; each contribution is an int32
-// against the per-(brick, group) scale and the cells hold the group's exact
-// sums (one atomic per segment).  Interpolated: 32-bit cells (LDS atomics
-// about 1.4x faster than 64-bit ones, and eight per sample); the scale is
-// chosen per round so that everything the round's rays can add to one cell
-// fits (cmax sum_r |y_r|, cmax the most one ray adds to one cell per unit
-// y), the cells are flushed after every round, and contributions are
-// rounded to nearest.
+// Accumulator cells: 32-bit (LDS atomics about 1.4x faster than 64-bit
+// ones); the scale is chosen per round so that everything the round's rays
+// can add to one cell fits (cmax sum_r |y_r|, cmax the most one ray adds to
+// one cell per unit y: one chord for Siddon, whose rays cross a cell once;
+// K samples of ds for the interpolated adjoint), the cells are flushed
+// after every round, and contributions are rounded to nearest.  The Siddon
+// adjoint's alternative (CTMI_BWD_SID_ACC32=0) keeps 64-bit cells with one
+// scale per (brick, group) from the group's largest |y|, summed exactly over
+// the group: 10 % slower with the layer walk (559 against 504 ms at 512^3 x
+// 720; with the plane-by-plane walk it had been the faster one).
 #ifndef CTMI_BWD_SID_ACC32
-#define CTMI_BWD_SID_ACC32 0
+#define CTMI_BWD_SID_ACC32 1
 #endif
 constexpr bool SID_ACC32 = CTMI_BWD_SID_ACC32 != 0;
 typedef std::conditional<SID_ACC32, int, u64>::type SAcc;
@@ -484,7 +484,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                     __syncthreads();
                     continue;
                 }
-                ex = fixed_exp(cmax, ysum);
+                // (a sum of finite values overflows only when some |y| is near
+                // FLT_MAX; 256 values of at most 2^128 bound it by 2^136)
+                ex = ysum <= 0x1.fffffep127f ? fixed_exp(cmax, ysum) : fixed_exp(cmax, 0x1p127f) - 9;
             }
             // scaled before the length factor: |y 2^e| <= 2^30 / cmax
             if (cnt > 0) t_y[tid] = __builtin_ldexpf(yr, ex) * yl_;

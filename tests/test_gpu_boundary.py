@@ -104,10 +104,10 @@ def test_adjoint_is_linear_at_extreme_scales(P, kind):
     """A^T(c y) = c A^T(y): exact for powers of two far outside the usual
     range (the fixed-point scale follows the data's exponent), and to the
     fixed point's resolution for other factors: each contribution is
-    truncated to a unit of 2^-30 of its group's bound, and that bound moves
-    with the factor's mantissa.  The interpolated adjoint bounds a round of
-    up to 512 rays by their summed |y|, so its units are coarser (about
-    1e-6 relative on this case) than the Siddon adjoint's per-view maxima."""
+    rounded to a unit of 2^-30 of its round's bound (the round's summed |y|
+    times the most one ray adds to a cell: up to 256 Siddon rays, 512
+    interpolated), and that bound moves with the factor's mantissa (about
+    1e-6 relative on this case)."""
     geo, ang = RAGGED, _angles(12, 4)
     plan = P.Plan(geo, ang)
     y = synth.uniform_projections(geo, len(ang), 5)
@@ -117,7 +117,7 @@ def test_adjoint_is_linear_at_extreme_scales(P, kind):
         assert np.array_equal(got, base * 2.0 ** k), (kind, k)
     for c in (1e-32, 3e-20, 7e25):
         got = _host(plan.backproject(_dev(y * np.float32(c)), kind=kind)).astype(np.float64)
-        assert _rel(got / c, base) < (1e-6 if kind == "siddon" else 4e-6), (kind, c)
+        assert _rel(got / c, base) < 4e-6, (kind, c)
 
 
 @pytest.mark.parametrize("kind", ["siddon", "interp"])
