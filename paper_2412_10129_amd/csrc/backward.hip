@@ -387,7 +387,14 @@ __device__ __forceinline__ SiddonAxis table_axis(float inv, float c)
     return r;
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
+// waves per SIMD the Siddon adjoint's registers are sized for: its 32-bit
+// cells leave room for five workgroups per CU (31 KB of LDS each); 3 / 4 / 5
+// measured 506 / 505 / 500 ms at 512^3 x 720 (five spill a few registers
+// outside the walk)
+#ifndef CTMI_BWD_SID_WAVES
+#define CTMI_BWD_SID_WAVES 5
+#endif
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CTMI_BWD_SID_WAVES, 8))) k_backward_siddon(const float* __restrict__ proj, float* __restrict__ vol,
                                                          const ViewGeo* __restrict__ tab,
                                                          const ViewGeo64* __restrict__ tab64, int view0, int nviews,
                                                          VolDims v, DetDims det, BrickMap m, float beta, float cmax)
