@@ -613,6 +613,103 @@ __global__ void k_up2_dgrad(const u16* __restrict__ gr, int ldg, int cout, const
     *reinterpret_cast<uint4*>(out + cv * ldo + cg * 8) = pack8(acc);
 }
 
+// The same data gradient on the MFMA: D[ci][v] = sum_k W'[ci][k] G[k][v]
+// with k = s cout + co, W'[ci][s cout + co] = w[co][s][ci] and G[k][v] =
+// g[2v + s][co].  A wave owns 2 x 16 coarse voxels (B columns: lane li
+// reads 8 consecutive co of fine voxel 2v + s, one 16-byte load); the
+// workgroup stages each 32-wide k chunk of W' transposed in LDS ([ci][32],
+// one 16-byte A fragment per lane and ci tile).  Lane (li, g) ends with
+// ci = 16 nt + 4 g .. + 3 of voxel v0 + li.
+#ifndef CTMI_UP2_DGRAD_MFMA
+#define CTMI_UP2_DGRAD_MFMA 1
+#endif
+constexpr int UPD_VG = 2;   // 16-voxel groups per wave
+template <int NT>
+__global__ __launch_bounds__(256) void k_up2_dgrad_mfma(const u16* __restrict__ gr, int ldg, int cout,
+                                                        const u16* __restrict__ wt, const u16* __restrict__ below,
+                                                        int ldb, int n, int d, int h, int w, u16* __restrict__ out,
+                                                        int ldo)
+{
+    constexpr int CIN = 16 * NT, WS = 40;   // LDS row stride (u16): 32 k + 8 pad
+    __shared__ __attribute__((aligned(16))) u16 wl[CIN * WS];
+    const int lane = threadIdx.x & 63, g = lane >> 4, li = lane & 15;
+    const int64_t nvox = (int64_t)n * d * h * w;
+    const int64_t vw = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * UPD_VG);   // the wave's first voxel
+    const int D2 = 2 * d, H2 = 2 * h, W2 = 2 * w;
+    int64_t fb[UPD_VG];   // fine index of sub-position 0 of each group's voxel
+    bool vok[UPD_VG];
+#pragma unroll
+    for (int q = 0; q < UPD_VG; ++q) {
+        const int64_t v = vw + 16 * q + li;
+        vok[q] = v < nvox;
+        int64_t r = vok[q] ? v : 0;
+        const int cx = (int)(r % w);
+        r /= w;
+        const int cy = (int)(r % h);
+        r /= h;
+        const int cz = (int)(r % d);
+        const int nb = (int)(r / d);
+        fb[q] = (((int64_t)nb * D2 + 2 * cz) * H2 + 2 * cy) * W2 + 2 * cx;
+    }
+    f32x4 acc[UPD_VG][NT];
+#pragma unroll
+    for (int q = 0; q < UPD_VG; ++q)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[q][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int K = 8 * cout;
+    for (int kc = 0; kc < K; kc += 32) {
+        __syncthreads();   // the previous chunk's fragments have been read
+        for (int i = threadIdx.x; i < CIN * 32; i += 256) {
+            const int ci = i % CIN, kk = i / CIN;   // consecutive threads read consecutive ci
+            const int k = kc + kk, s = k / cout, co = k - s * cout;
+            wl[ci * WS + kk] = wt[((size_t)co * 8 + s) * CIN + ci];
+        }
+        __syncthreads();
+        const int k = kc + 8 * g, s = k / cout, co0 = k - s * cout;
+        const int64_t so = ((int64_t)(s >> 2) * H2 + ((s >> 1) & 1)) * W2 + (s & 1);   // fine offset of sub-position s
+        bf16x8 af[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            af[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(&wl[(nt * 16 + li) * WS + 8 * g]));
+#pragma unroll
+        for (int q = 0; q < UPD_VG; ++q) {
+            const uint4 gq = vok[q] ? *reinterpret_cast<const uint4*>(gr + (fb[q] + so) * ldg + co0)
+                                    : make_uint4(0, 0, 0, 0);
+            const bf16x8 gb = as_bf16x8(gq);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[q][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[nt], gb, acc[q][nt], 0, 0, 0);
+        }
+    }
+    // explicit wait states between the last MFMAs and the reads of their
+    // results (as in k_up2_mfma)
+#pragma unroll
+    for (int q = 0; q < UPD_VG; ++q)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" : "+a"(acc[q][nt]));
+#pragma unroll
+    for (int q = 0; q < UPD_VG; ++q) {
+        if (!vok[q]) continue;
+        const int64_t v = vw + 16 * q + li;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int ci = nt * 16 + 4 * g;
+            float o[4] = {acc[q][nt][0], acc[q][nt][1], acc[q][nt][2], acc[q][nt][3]};
+            if (below) {
+                const uint2 m = *reinterpret_cast<const uint2*>(below + v * ldb + ci);
+                if (!bf_pos((u16)(m.x & 0xFFFF))) o[0] = 0.0f;
+                if (!bf_pos((u16)(m.x >> 16))) o[1] = 0.0f;
+                if (!bf_pos((u16)(m.y & 0xFFFF))) o[2] = 0.0f;
+                if (!bf_pos((u16)(m.y >> 16))) o[3] = 0.0f;
+            }
+            uint2 pk;
+            pk.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+            pk.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+            *reinterpret_cast<uint2*>(out + v * ldo + ci) = pk;
+        }
+    }
+}
+
 // weight gradient of up2: dw[co][s][ci] = sum_v g[2v + s][co] x[v][ci].
 // Block = (s, co tile of 16, ci tile of 16) x voxel split; thread = one
 // (co, ci) output; 64 coarse voxels per LDS round.
@@ -888,7 +985,15 @@ hipError_t launch_unet_up2_dgrad(const uint16_t* g, int ldg, int cout, const uin
                                  const uint16_t* below, int ldb, int n, int d, int h, int w, uint16_t* out, int ldo,
                                  hipStream_t s)
 {
-    const int64_t total = (int64_t)n * d * h * w * (cin / 8);
+    const int64_t nvox = (int64_t)n * d * h * w;
+    if (CTMI_UP2_DGRAD_MFMA && cout % 16 == 0 && (cin == 32 || cin == 64 || cin == 128)) {
+        const unsigned blocks = (unsigned)((nvox + 4 * 16 * UPD_VG - 1) / (4 * 16 * UPD_VG));
+        if (cin == 32) k_up2_dgrad_mfma<2><<<blocks, 256, 0, s>>>(g, ldg, cout, wt, below, ldb, n, d, h, w, out, ldo);
+        else if (cin == 64) k_up2_dgrad_mfma<4><<<blocks, 256, 0, s>>>(g, ldg, cout, wt, below, ldb, n, d, h, w, out, ldo);
+        else k_up2_dgrad_mfma<8><<<blocks, 256, 0, s>>>(g, ldg, cout, wt, below, ldb, n, d, h, w, out, ldo);
+        return hipGetLastError();
+    }
+    const int64_t total = nvox * (cin / 8);
     k_up2_dgrad<<<blocks_for(total, 256), 256, 0, s>>>(g, ldg, cout, wt, cin, below, ldb, n, d, h, w, out, ldo);
     return hipGetLastError();
 }

@@ -181,6 +181,28 @@ def test_pool_up_skip_head_kernels(P):
     _bf16_close(_np(dze), (U.pool2_adjoint(dp) + gcat[..., cout:]) * (e > 0))
 
 
+@pytest.mark.parametrize("cin,cout,mask", [(32, 16, True), (64, 32, False), (128, 64, True)])
+def test_up2_dgrad_every_level(P, cin, cout, mask):
+    """The up-convolution's data gradient at each level's channel counts
+    (the MFMA kernel's three ci-tile counts), with and without the ReLU mask
+    of its input, on a ragged coarse grid (the last wave partly empty),
+    against the oracle's adjoint of the transposed convolution."""
+    L = _lib()
+    lib = L.lib()
+    n, d, h, w = 1, 3, 5, 7
+    wt = synth.bf16_values((cout, 8, cin), 301 + cin, -0.3, 0.3)
+    gr = synth.bf16_values((n, 2 * d, 2 * h, 2 * w, cout + 8), 302 + cin)
+    below = synth.bf16_values((n, d, h, w, cin), 303 + cin)
+    tw, tg, tbel = _bf(wt), _bf(gr), _bf(below)
+    dx = torch.empty((n, d, h, w, cin), dtype=torch.bfloat16, device="cuda")
+    L.check(lib.ctmi_upsample2_dgrad(n, d, h, w, _p(tg), cout, cout + 8, _p(tw), cin, _p(tbel) if mask else None,
+                                     cin, _p(dx), cin, _s()))
+    want = U.up2_dgrad(gr[..., :cout], wt)
+    if mask:
+        want = want * (below > 0)
+    _bf16_close(_np(dx), want)
+
+
 def test_head_loss_and_adam(P):
     L = _lib()
     lib = L.lib()
