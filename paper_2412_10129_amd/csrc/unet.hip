@@ -768,6 +768,90 @@ __global__ __launch_bounds__(256) void k_up2_wgrad(const u16* __restrict__ x, in
     part[((size_t)(cot * 16 + co_l) * 8 + s) * cin + cit * 16 + ci_l] = acc;
 }
 
+// The same weight gradient on the MFMA: per (s, co tile, ci tile) block a
+// 16 x 16 GEMM with K = coarse voxels.  Both operands need 8 consecutive
+// voxels per lane, so each wave stages its 64-voxel chunk transposed in
+// LDS (g rows as [co][voxel], x rows as [ci][voxel]) and issues two MFMAs;
+// the block's four waves take interleaved chunks of its voxel share and add
+// their 16 x 16 sums in a fixed order at the end (deterministic partials, the
+// same layout as k_up2_wgrad's).
+#ifndef CTMI_UP2_WGRAD_MFMA
+#define CTMI_UP2_WGRAD_MFMA 1
+#endif
+constexpr int UPW_S = 72;   // LDS row stride (u16) of a transposed chunk
+__global__ __launch_bounds__(256) void k_up2_wgrad_mfma(const u16* __restrict__ x, int ldx, int cin,
+                                                        const u16* __restrict__ gr, int ldg, int cout, int n, int d,
+                                                        int h, int w, float* __restrict__ partial)
+{
+    __shared__ __attribute__((aligned(16))) u16 gt[4][16 * UPW_S];
+    __shared__ __attribute__((aligned(16))) u16 xt[4][16 * UPW_S];
+    __shared__ float red[4][256];
+    const int ci_tiles = cin / 16, co_tiles = cout / 16;
+    int b = blockIdx.x;
+    const int cit = b % ci_tiles;
+    b /= ci_tiles;
+    const int cot = b % co_tiles;
+    const int s = b / co_tiles;
+    const int split = blockIdx.y, nsplit = gridDim.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
+    const int64_t nvox = (int64_t)n * d * h * w;
+    const int64_t nchunks = (nvox + 63) / 64;
+    const int64_t mine = nchunks > split ? (nchunks - split + nsplit - 1) / nsplit : 0;   // chunks of this split
+    const int64_t rounds = (mine + 3) / 4;
+    const int D2 = 2 * d, H2 = 2 * h, W2 = 2 * w;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t it = 0; it < rounds; ++it) {
+        const int64_t j = 4 * it + wave;               // this wave's chunk in the split's list
+        const int64_t v = (split + j * nsplit) * 64 + lane;
+        uint4 g0 = make_uint4(0, 0, 0, 0), g1 = g0, x0 = g0, x1 = g0;
+        if (j < mine && v < nvox) {
+            int64_t r = v;
+            const int cx = (int)(r % w);
+            r /= w;
+            const int cy = (int)(r % h);
+            r /= h;
+            const int cz = (int)(r % d);
+            const int nb = (int)(r / d);
+            const int64_t fv = (((int64_t)nb * D2 + 2 * cz + (s >> 2)) * H2 + 2 * cy + ((s >> 1) & 1)) * W2 + 2 * cx +
+                               (s & 1);
+            const u16* gp = gr + fv * ldg + cot * 16;
+            const u16* xp = x + v * ldx + cit * 16;
+            g0 = *reinterpret_cast<const uint4*>(gp);
+            g1 = *reinterpret_cast<const uint4*>(gp + 8);
+            x0 = *reinterpret_cast<const uint4*>(xp);
+            x1 = *reinterpret_cast<const uint4*>(xp + 8);
+        }
+        __syncthreads();   // every wave has read the previous chunk's fragments
+        {
+            const uint32_t gw[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+            const uint32_t xw[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                gt[wave][(2 * c) * UPW_S + lane] = (u16)(gw[c] & 0xFFFFu);
+                gt[wave][(2 * c + 1) * UPW_S + lane] = (u16)(gw[c] >> 16);
+                xt[wave][(2 * c) * UPW_S + lane] = (u16)(xw[c] & 0xFFFFu);
+                xt[wave][(2 * c + 1) * UPW_S + lane] = (u16)(xw[c] >> 16);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 64; kk += 32) {
+            const uint4 af = *reinterpret_cast<const uint4*>(&gt[wave][li * UPW_S + kk + 8 * g]);
+            const uint4 bf = *reinterpret_cast<const uint4*>(&xt[wave][li * UPW_S + kk + 8 * g]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(af), as_bf16x8(bf), acc, 0, 0, 0);
+        }
+    }
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" : "+a"(acc));
+    // lane (li, g) holds dW rows co = 4 g .. 4 g + 3 of column ci = li
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wave][(4 * g + e) * 16 + li] = acc[e];
+    __syncthreads();
+    const int t = threadIdx.x, co_l = t >> 4, ci_l = t & 15;
+    const float sum = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    float* part = partial + (size_t)split * cout * 8 * cin;
+    part[((size_t)(cot * 16 + co_l) * 8 + s) * cin + cit * 16 + ci_l] = sum;
+}
+
 // residual head: out[v] = x_in[v] + hb + sum_c hw[c] a[v][c] (FP32)
 __global__ void k_head(const float* __restrict__ xin, const u16* __restrict__ act, int lda, int c,
                        const u16* __restrict__ hw, const float* __restrict__ hb, int64_t nvox, float* __restrict__ out)
@@ -1020,7 +1104,10 @@ hipError_t launch_unet_up2_wgrad(const uint16_t* x, int ldx, int cin, const uint
 {
     const int nsplit = unet_up2_wgrad_splits(n, d, h, w, cin, cout);
     dim3 grid(8 * (cin / 16) * (cout / 16), nsplit);
-    k_up2_wgrad<<<grid, 256, 0, s>>>(x, ldx, cin, g, ldg, cout, n, d, h, w, ws);
+    if (CTMI_UP2_WGRAD_MFMA)
+        k_up2_wgrad_mfma<<<grid, 256, 0, s>>>(x, ldx, cin, g, ldg, cout, n, d, h, w, ws);
+    else
+        k_up2_wgrad<<<grid, 256, 0, s>>>(x, ldx, cin, g, ldg, cout, n, d, h, w, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nw = (int64_t)cout * 8 * cin;

@@ -182,11 +182,12 @@ def test_pool_up_skip_head_kernels(P):
 
 
 @pytest.mark.parametrize("cin,cout,mask", [(32, 16, True), (64, 32, False), (128, 64, True)])
-def test_up2_dgrad_every_level(P, cin, cout, mask):
-    """The up-convolution's data gradient at each level's channel counts
-    (the MFMA kernel's three ci-tile counts), with and without the ReLU mask
-    of its input, on a ragged coarse grid (the last wave partly empty),
-    against the oracle's adjoint of the transposed convolution."""
+def test_up2_gradients_every_level(P, cin, cout, mask):
+    """The up-convolution's data gradient (with and without the ReLU mask of
+    its input) and weight gradient at each level's channel counts (the MFMA
+    kernels' tile counts), on a ragged coarse grid (the last wave and the
+    last voxel chunk partly empty), against the oracle's adjoints of the
+    transposed convolution."""
     L = _lib()
     lib = L.lib()
     n, d, h, w = 1, 3, 5, 7
@@ -201,6 +202,14 @@ def test_up2_dgrad_every_level(P, cin, cout, mask):
     if mask:
         want = want * (below > 0)
     _bf16_close(_np(dx), want)
+    x = synth.bf16_values((n, d, h, w, cin + 16), 304 + cin)
+    tx = _bf(x)
+    ws = _ws(lib.ctmi_upsample2_wgrad_workspace_bytes(n, d, h, w, cin, cout))
+    dw = torch.empty((cout, 8, cin), device="cuda")
+    L.check(lib.ctmi_upsample2_wgrad(n, d, h, w, _p(tx), cin, cin + 16, _p(tg), cout, cout + 8, _p(dw), None, 0,
+                                     _p(ws), ws.numel() * 4, _s()))
+    wdw, _ = U.up2_wgrad(x[..., :cin], gr[..., :cout])
+    assert _rel(dw.cpu().numpy(), wdw) < 1e-5, _rel(dw.cpu().numpy(), wdw)
 
 
 def test_head_loss_and_adam(P):
